@@ -1,0 +1,302 @@
+/*
+ * mbrank — ranking of many-body occupation patterns, on-the-fly Hubbard H·x and
+ * Lanczos ground-state search on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Wallerberger and K. Held, "Trie-based ranking of quantum many-body
+ * states", arXiv:2203.04158.  Section/equation references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A state is an M-bit occupation pattern: bit i is orbital i (Sec. II).  Patterns
+ *    are passed as uint32 (M <= 32) or uint64 (M <= 64) arrays; `width_bits` (32|64)
+ *    names which.  For the spin-resolved Hamiltonians orbital i (< L) is site i
+ *    spin-down and orbital L+i is site i spin-up (spin-down in the least
+ *    significant bits, as assumed for Eq. rankupdown).
+ *  - A sector is the set of patterns satisfying a list of popcount windows,
+ *    ordered by ascending numeric value, which is the lexicographic order of
+ *    Sec. III (c_N first).  rank(alpha) is the position of alpha in that order.
+ *  - Every call returns an mbr_status; 0 is success and the negative codes are
+ *    listed below.  mbr_last_error() returns a text for the last failing call of
+ *    the calling thread.
+ *  - Pointers named d_* are device pointers (HIP device memory) owned by the
+ *    caller, who keeps them alive until the work queued on `stream` completes.
+ *    Other pointers are host memory, read during the call only.
+ *  - Handles (mbr_sector, mbr_ranker, mbr_hubbard, mbr_lanczos) are opaque,
+ *    owned by the library, hold their own device tables, and are released with
+ *    the matching *_destroy.  A handle lives on the device that was current when
+ *    it was created.  Read-only use of one handle from several streams is safe.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.  Batched
+ *    calls only enqueue work (no host synchronisation) unless stated otherwise.
+ *  - Per-element failures are sentinels, not status codes: a pattern outside the
+ *    ranker's sector ranks to MBR_NOT_FOUND (all patterns with bits at or above M,
+ *    with the wrong particle numbers, or absent from a trie's sector); an unrank
+ *    index >= the sector size yields an all-ones pattern.
+ */
+#ifndef MBRANK_H
+#define MBRANK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mbr_status;
+#define MBR_OK            0
+#define MBR_EINVAL       (-1) /* argument outside its documented range */
+#define MBR_ENOMEM       (-2) /* device or host allocation failed */
+#define MBR_EHIP         (-3) /* a HIP runtime call failed */
+#define MBR_ENOTSORTED   (-4) /* caller-supplied state list not strictly ascending */
+#define MBR_EDUP         (-5) /* caller-supplied state list has a repeated entry */
+#define MBR_ERANGE       (-6) /* an index or size exceeds what the handle supports */
+#define MBR_EUNSUPPORTED (-7) /* valid request this build does not implement */
+
+#define MBR_NOT_FOUND 0xFFFFFFFFu
+
+/* Text for a status code (static storage). */
+const char *mbr_status_str(mbr_status s);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *mbr_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t mbr_version(void);
+
+/* ======================================================================== */
+/* Sectors (Sec. II: particle-number blocks, Eq. mvblock; Sec. IV: further   */
+/* quantum numbers by filtering)                                            */
+/* ======================================================================== */
+
+/* Popcount window: lo <= popcount(alpha AND mask) <= hi. */
+typedef struct {
+    uint64_t mask;
+    int32_t lo;
+    int32_t hi;
+} mbr_popc_cons;
+
+typedef struct mbr_sector mbr_sector;
+
+/* Enumerate, on the device, every M-bit pattern that satisfies all n_cons
+ * windows, in ascending order (this list is the unrank table, Sec. II and
+ * Sec. III.A).  M in 1..64; width_bits 32 (needs M <= 32) or 64.  If the windows
+ * fix the total particle number (one window on all M bits with lo == hi, or
+ * disjoint fixed windows covering all M bits) only the C(M,N) patterns of that
+ * number are visited; otherwise M <= 32 and all 2^M patterns are tested.
+ * Sectors must hold fewer than 2^32 - 1 states (ERANGE).  Synchronises `stream`
+ * (the size must be known to allocate).  *out receives the handle. */
+mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
+                            const mbr_popc_cons *cons, mbr_sector **out, void *stream);
+
+/* Number of states in the sector. */
+mbr_status mbr_sector_size(const mbr_sector *s, uint64_t *n);
+
+/* Borrowed device pointer to the ascending state list (uint32 or uint64 per
+ * width_bits), valid until mbr_sector_destroy. */
+mbr_status mbr_sector_states(const mbr_sector *s, const void **d_states);
+
+mbr_status mbr_sector_destroy(mbr_sector *s);
+
+/* Unrank by the stored list (Sec. II): d_out[j] = states[d_idx[j]] for j < n,
+ * or all ones when d_idx[j] >= size.  d_out has the sector's width. */
+mbr_status mbr_unrank_batch(const mbr_sector *s, const uint32_t *d_idx, uint64_t n,
+                            void *d_out, void *stream);
+
+/* ======================================================================== */
+/* Rankers                                                                   */
+/* ======================================================================== */
+
+typedef struct mbr_ranker mbr_ranker;
+
+#define MBR_RANKER_STAGGERED 1
+#define MBR_RANKER_SPIN      2
+#define MBR_RANKER_TRIE      3
+#define MBR_RANKER_LEARNED   4
+
+typedef struct {
+    int32_t kind;       /* MBR_RANKER_* */
+    int32_t M;          /* pattern length in bits */
+    int32_t k;          /* chunk width (bits per lookup) */
+    int32_t width_bits; /* query width: 32 or 64 */
+    uint64_t n_states;  /* size of the sector ranked into */
+    uint64_t bytes;     /* device bytes of the ranker's tables */
+    int32_t levels;     /* lookups per query (chunks or trie levels) */
+    int32_t reserved;
+} mbr_ranker_info;
+
+/* Staggered lookup (Sec. III.B, Fig. fastrank, Eq. partrank): tables of the
+ * partial ranks rank(r, M', N') for chunks of k bits taken from the least
+ * significant end, M' = 0, k, 2k, ..., rows N' = 0..min(M', Nmax), chunk value r
+ * varying fastest; entries built through Eq. reuse.  When k does not divide M
+ * the last chunk holds M mod k bits.  N >= 0 ranks within C^M_N (patterns of
+ * other popcount rank to MBR_NOT_FOUND, Nmax = N); N = -1 builds the universal
+ * table (Nmax = M) and ranks any pattern within its own particle-number block.
+ * M in 1..64, k in 1..16, width_bits 32|64. */
+mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t width_bits,
+                                      mbr_ranker **out, void *stream);
+
+/* Copy a staggered ranker's table to host memory as uint64 entries:
+ * entry (chunk c, N', r) is written at index (row(c, N') << k) + r with
+ * row(c, N') = sum_{c' < c} (min(c' k, Nmax) + 1) + N'.  *n_entries receives
+ * the count; nothing is written when host_out is NULL or cap is too small.
+ * Synchronises `stream`. */
+mbr_status mbr_staggered_table_copy(const mbr_ranker *r, uint64_t *host_out, uint64_t cap,
+                                    uint64_t *n_entries, void *stream);
+
+/* Spin-resolved rank (Eq. rankupdown, with the multiplier read as the number of
+ * spin-down configurations): for a 2L-bit pattern with spin-down in bits 0..L-1,
+ * rank = rank_{N_up}(alpha_up) * C(L, n_dn) + rank_{N_dn}(alpha_dn), each half
+ * ranked by the staggered lookup with chunk width k.  L in 1..32. */
+mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t k,
+                                 mbr_ranker **out, void *stream);
+
+/* Packed radix-2^k trie over a sector (Sec. IV, Fig. trie, Fig. trielookup):
+ * chunks dispatched from the least significant end, one array per level, each
+ * node spanning its first to last occurring child, unused slots zero and the
+ * arrays padded so that any pattern's walk stays in bounds; after the walk,
+ * membership is checked against the sector's list (safe lookup, Sec. IV).
+ * k in 1..16.  The trie keeps a reference to `s`: destroy it before `s`. */
+mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
+
+/* Learned index (extension, not in the paper): a 32->64->64->1 ReLU network
+ * with bf16 weights and fp32 accumulation predicts rank/size from the 32 bit
+ * features; it is trained on the GPU on the sector's own list.  The largest
+ * prediction error e over all members (measured with the query kernel itself)
+ * bounds an exact bisection in states[p-e .. p+e]; sectors whose e exceeds
+ * opts->max_window are ranked by `fallback` instead (the fallback must rank the
+ * same sector; the learned ranker keeps a reference to it and to `s`).
+ * width_bits must be 32. */
+typedef struct {
+    int32_t epochs;     /* passes over the sector list */
+    int32_t batch;      /* samples per optimiser step (multiple of 256) */
+    float lr;           /* Adam step size */
+    uint64_t seed;      /* weight initialisation and sample order */
+    uint64_t max_window;/* largest e still served by the window search */
+    uint64_t samples_per_epoch; /* 0 = whole list */
+} mbr_learned_opts;
+
+mbr_status mbr_learned_train(const mbr_sector *s, const mbr_learned_opts *opts,
+                             const mbr_ranker *fallback, mbr_ranker **out, void *stream);
+
+/* Recorded maximum prediction error e of a learned ranker, and whether it
+ * answers through its own window search (1) or through the fallback (0). */
+mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses_window);
+
+/* Copy the learned ranker's parameters to host memory as fp32 in the order
+ * W1[64][32], b1[64], W2[64][64], b2[64], w3[64], b3 (6337 values); these are
+ * the bf16-rounded weights the query kernel uses.  Synchronises `stream`. */
+mbr_status mbr_learned_params(const mbr_ranker *r, float *host_out, void *stream);
+
+/* Learned-network primitives exposed for checking against an fp64 reference:
+ * forward pass (d_pred[B]) and mean-squared-loss gradients (d_grad[6337], same
+ * order as mbr_learned_params) for B patterns d_q (uint32) and targets d_tgt,
+ * with fp32 parameters d_params (rounded to bf16 inside, as in training).
+ * B must be a multiple of 64. */
+mbr_status mbr_mlp_forward(const float *d_params, const uint32_t *d_q, int32_t B,
+                           float *d_pred, void *stream);
+mbr_status mbr_mlp_gradients(const float *d_params, const uint32_t *d_q, const float *d_tgt,
+                             int32_t B, float *d_grad, float *d_loss, void *stream);
+
+mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info);
+
+/* Rank n patterns: d_rank[j] = rank of d_q[j] in the ranker's sector or
+ * MBR_NOT_FOUND.  d_q has the ranker's width. */
+mbr_status mbr_rank_batch(const mbr_ranker *r, const void *d_q, uint64_t n, uint32_t *d_rank,
+                          void *stream);
+
+mbr_status mbr_ranker_destroy(mbr_ranker *r);
+
+/* ======================================================================== */
+/* Hubbard-type Hamiltonians applied on the fly (Eq. Talpha, Eq. mvblock,     */
+/* Eq. Hring generalised to a bond list)                                     */
+/* ======================================================================== */
+
+typedef struct mbr_hubbard mbr_hubbard;
+
+typedef struct {
+    int32_t i, j; /* sites, 0 <= i, j < L, i != j */
+    double t;     /* amplitude: H contains -t (c+_{i s} c_{j s} + c+_{j s} c_{i s}) */
+} mbr_bond;
+
+typedef struct {
+    int32_t n_up, n_dn;
+} mbr_spin_sector;
+
+#define MBR_F64 0
+#define MBR_F32 1
+
+typedef struct {
+    int32_t L;                       /* sites, 1..16 */
+    int32_t n_bonds;                 /* 0..64 */
+    const mbr_bond *bonds;
+    const double *eps;               /* on-site energies [L] or NULL */
+    const double *U;                 /* on-site interaction [L] or NULL */
+    int32_t n_sectors;               /* 1..1024 spin sectors, concatenated */
+    const mbr_spin_sector *sectors;
+    int32_t precision;               /* MBR_F64 or MBR_F32 vectors */
+    int32_t k;                       /* half-pattern chunk width, 0 = automatic */
+} mbr_hubbard_desc;
+
+/* H = -sum_b t_b sum_s (c+_{i s} c_{j s} + h.c.) + sum_i U_i n_{i up} n_{i dn}
+ *     + sum_{i s} eps_i n_{i s}, restricted to the listed (N_up, N_dn) sectors.
+ * Vectors are the concatenation of the sectors in list order; within a sector
+ * the index is rank_up * C(L, n_dn) + rank_dn (Eq. rankupdown). */
+mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void *stream);
+
+/* Total dimension and, if offsets != NULL, the n_sectors+1 sector offsets. */
+mbr_status mbr_hubbard_dim(const mbr_hubbard *h, uint64_t *total, uint64_t *offsets);
+
+/* d_y = H d_x in the gather form of Eq. Talpha2: one output row per lane group,
+ * no atomics.  x and y are fp64 or fp32 per the descriptor and must not alias. */
+mbr_status mbr_hubbard_apply(const mbr_hubbard *h, const void *d_x, void *d_y, void *stream);
+
+mbr_status mbr_hubbard_destroy(mbr_hubbard *h);
+
+/* ======================================================================== */
+/* Lanczos ground-state search over every sector of a Hamiltonian            */
+/* ======================================================================== */
+
+typedef struct mbr_lanczos mbr_lanczos;
+
+typedef struct {
+    int32_t max_steps;     /* Krylov steps kept per sector, 1..4096 */
+    int32_t reorth;        /* 1: full classical Gram-Schmidt each step (fp64 coefficients) */
+    int32_t batched;       /* 1: all sectors per kernel launch; 0: one launch set per sector */
+    int32_t use_graph;     /* 1: replay a captured hipGraph per step */
+    double breakdown_tol;  /* relative beta below which a sector stops (0 = default) */
+} mbr_lanczos_opts;
+
+/* Lanczos recurrence u = H v_j - beta_{j-1} v_{j-1}, alpha_j = <v_j, u>,
+ * w = u - alpha_j v_j, beta_j = |w|, v_{j+1} = w / beta_j, run independently per
+ * sector.  Vectors have the Hamiltonian's precision; alpha, beta and every dot
+ * product accumulate in fp64. */
+mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o,
+                              mbr_lanczos **out);
+
+/* Set the start vector (fp64, the Hamiltonian's total dimension; each sector's
+ * part is normalised separately) and reset the step count. */
+mbr_status mbr_lanczos_start(mbr_lanczos *lz, const double *d_v0, void *stream);
+
+/* Enqueue nsteps Lanczos steps. */
+mbr_status mbr_lanczos_step(mbr_lanczos *lz, int32_t nsteps, void *stream);
+
+/* Lowest Ritz value per sector (tridiagonal solved on the device by Sturm
+ * bisection in fp64) and the steps each sector completed.  Either output may be
+ * NULL.  Synchronises `stream`. */
+mbr_status mbr_lanczos_result(mbr_lanczos *lz, double *e0, int32_t *steps_done, void *stream);
+
+/* Copy alpha and beta (n_sectors x max_steps each, row per sector) to host.
+ * Synchronises `stream`. */
+mbr_status mbr_lanczos_coeffs(mbr_lanczos *lz, double *alpha, double *beta, void *stream);
+
+mbr_status mbr_lanczos_destroy(mbr_lanczos *lz);
+
+/* Lowest eigenvalue of n_batch symmetric tridiagonal matrices by Sturm-count
+ * bisection in fp64: matrix b has diagonal d_alpha[b*ld .. b*ld+len_b-1] and
+ * off-diagonal d_beta[b*ld .. b*ld+len_b-2], len_b = d_len[b] (1..ld).
+ * Result to d_e0[b]. */
+mbr_status mbr_tridiag_lowest(const double *d_alpha, const double *d_beta, const int32_t *d_len,
+                              int32_t ld, int32_t n_batch, double *d_e0, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBRANK_H */

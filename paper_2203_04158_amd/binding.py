@@ -1,0 +1,420 @@
+"""Thin ctypes binding of libmbrank.so (the C ABI declared in include/mbrank.h).
+
+Only argument marshalling lives here: torch tensors supply device memory and
+streams, every computation runs in the HIP library.  Importing this module
+does not need a GPU; calling into the library does, and a missing library is
+an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbrank.so")
+NOT_FOUND = 0xFFFFFFFF
+
+RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED = 1, 2, 3, 4
+F64, F32 = 0, 1
+
+_lib = None
+
+
+class MbrError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str):
+        super().__init__(f"{fn}: status {status} ({detail})")
+        self.status = status
+
+
+class PopcCons(C.Structure):
+    _fields_ = [("mask", C.c_uint64), ("lo", C.c_int32), ("hi", C.c_int32)]
+
+
+class RankerInfo(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("M", C.c_int32), ("k", C.c_int32),
+                ("width_bits", C.c_int32), ("n_states", C.c_uint64), ("bytes", C.c_uint64),
+                ("levels", C.c_int32), ("reserved", C.c_int32)]
+
+
+class LearnedOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("seed", C.c_uint64), ("max_window", C.c_uint64),
+                ("samples_per_epoch", C.c_uint64)]
+
+
+class Bond(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("t", C.c_double)]
+
+
+class SpinSector(C.Structure):
+    _fields_ = [("n_up", C.c_int32), ("n_dn", C.c_int32)]
+
+
+class HubbardDesc(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_bonds", C.c_int32), ("bonds", C.POINTER(Bond)),
+                ("eps", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
+                ("n_sectors", C.c_int32), ("sectors", C.POINTER(SpinSector)),
+                ("precision", C.c_int32), ("k", C.c_int32)]
+
+
+class LanczosOpts(C.Structure):
+    _fields_ = [("max_steps", C.c_int32), ("reorth", C.c_int32), ("batched", C.c_int32),
+                ("use_graph", C.c_int32), ("breakdown_tol", C.c_double)]
+
+
+_SIGS = {
+    "mbr_status_str": (C.c_char_p, [C.c_int32]),
+    "mbr_last_error": (C.c_char_p, []),
+    "mbr_version": (C.c_int32, []),
+    "mbr_sector_build": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(PopcCons),
+                                     C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_sector_size": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "mbr_sector_states": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mbr_sector_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_unrank_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "mbr_build_staggered_tables": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                               C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_staggered_table_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64,
+                                             C.POINTER(C.c_uint64), C.c_void_p]),
+    "mbr_build_spin_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_build_trie": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_learned_train": (C.c_int32, [C.c_void_p, C.POINTER(LearnedOpts), C.c_void_p,
+                                      C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_learned_max_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64),
+                                          C.POINTER(C.c_int32)]),
+    "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mbr_mlp_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_ranker_info_get": (C.c_int32, [C.c_void_p, C.POINTER(RankerInfo)]),
+    "mbr_rank_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "mbr_ranker_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_hubbard_create": (C.c_int32, [C.POINTER(HubbardDesc), C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_hubbard_dim": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p]),
+    "mbr_hubbard_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_hubbard_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_lanczos_create": (C.c_int32, [C.c_void_p, C.POINTER(LanczosOpts), C.POINTER(C.c_void_p)]),
+    "mbr_lanczos_start": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_lanczos_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mbr_lanczos_result": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_lanczos_coeffs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_lanczos_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_tridiag_lowest": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                       C.c_void_p, C.c_void_p]),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libmbrank.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same soname as the system one;
+        # loading torch first makes libmbrank bind to that runtime, so the process
+        # holds a single HIP runtime whose device memory and streams both sides share.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2203_04158_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, st: int) -> None:
+    if st != 0:
+        L = lib()
+        detail = L.mbr_last_error().decode() or L.mbr_status_str(st).decode()
+        raise MbrError(fn, st, detail)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# --------------------------------------------------------------------------- sectors
+class Sector:
+    def __init__(self, handle, M: int, width_bits: int):
+        self._h = handle
+        self.M, self.width_bits = M, width_bits
+        n = C.c_uint64()
+        _check("mbr_sector_size", lib().mbr_sector_size(self._h, C.byref(n)))
+        self.size = int(n.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def states(self, stream=None):
+        """The sorted state list as a new device tensor (int32/int64 storage)."""
+        torch = _torch()
+        idx = torch.arange(self.size, dtype=torch.int32, device="cuda")
+        return unrank_batch(self, idx, stream=stream)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mbr_sector_destroy(self._h)
+            self._h = None
+
+
+def sector_build(M: int, constraints, width_bits: int = 32, stream=None) -> Sector:
+    """constraints: iterable of (mask, lo, hi) popcount windows."""
+    cons = list(constraints)
+    arr = (PopcCons * max(1, len(cons)))(*[PopcCons(int(m), int(lo), int(hi)) for m, lo, hi in cons])
+    h = C.c_void_p()
+    _check("mbr_sector_build", lib().mbr_sector_build(M, width_bits, len(cons), arr, C.byref(h),
+                                                      _stream(stream)))
+    return Sector(h, M, width_bits)
+
+
+def unrank_batch(sector: Sector, idx, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        dt = torch.int32 if sector.width_bits == 32 else torch.int64
+        out = torch.empty(idx.numel(), dtype=dt, device="cuda")
+    _check("mbr_unrank_batch", lib().mbr_unrank_batch(sector.handle, _dptr(idx), idx.numel(),
+                                                      _dptr(out), _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------------------- rankers
+class Ranker:
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = keep  # handles this ranker references
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> RankerInfo:
+        i = RankerInfo()
+        _check("mbr_ranker_info_get", lib().mbr_ranker_info_get(self._h, C.byref(i)))
+        return i
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mbr_ranker_destroy(self._h)
+            self._h = None
+
+
+def build_staggered_tables(M: int, N: int, k: int, width_bits: int = 32, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_staggered_tables",
+           lib().mbr_build_staggered_tables(M, N, k, width_bits, C.byref(h), _stream(stream)))
+    return Ranker(h)
+
+
+def staggered_table(ranker: Ranker, stream=None) -> np.ndarray:
+    n = C.c_uint64()
+    L = lib()
+    _check("mbr_staggered_table_copy",
+           L.mbr_staggered_table_copy(ranker.handle, None, 0, C.byref(n), _stream(stream)))
+    out = np.zeros(n.value, dtype=np.uint64)
+    _check("mbr_staggered_table_copy",
+           L.mbr_staggered_table_copy(ranker.handle, C.c_void_p(out.ctypes.data), out.size,
+                                      C.byref(n), _stream(stream)))
+    return out
+
+
+def build_spin_ranker(L: int, n_up: int, n_dn: int, k: int, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_spin_ranker",
+           lib().mbr_build_spin_ranker(L, n_up, n_dn, k, C.byref(h), _stream(stream)))
+    return Ranker(h)
+
+
+def build_trie(sector: Sector, k: int, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_trie", lib().mbr_build_trie(sector.handle, k, C.byref(h), _stream(stream)))
+    return Ranker(h, keep=(sector,))
+
+
+def learned_train(sector: Sector, fallback: Ranker, epochs: int = 4, batch: int = 4096,
+                  lr: float = 1e-3, seed: int = 1, max_window: int = 1 << 16,
+                  samples_per_epoch: int = 0, stream=None) -> Ranker:
+    o = LearnedOpts(epochs, batch, lr, seed, max_window, samples_per_epoch)
+    h = C.c_void_p()
+    _check("mbr_learned_train", lib().mbr_learned_train(sector.handle, C.byref(o), fallback.handle,
+                                                        C.byref(h), _stream(stream)))
+    return Ranker(h, keep=(sector, fallback))
+
+
+def learned_max_error(ranker: Ranker):
+    e = C.c_uint64()
+    w = C.c_int32()
+    _check("mbr_learned_max_error", lib().mbr_learned_max_error(ranker.handle, C.byref(e), C.byref(w)))
+    return int(e.value), bool(w.value)
+
+
+def learned_params(ranker: Ranker, stream=None) -> np.ndarray:
+    out = np.zeros(6337, dtype=np.float32)
+    _check("mbr_learned_params", lib().mbr_learned_params(ranker.handle, C.c_void_p(out.ctypes.data),
+                                                          _stream(stream)))
+    return out
+
+
+def mlp_forward(params, q, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(q.numel(), dtype=torch.float32, device="cuda")
+    _check("mbr_mlp_forward", lib().mbr_mlp_forward(_dptr(params), _dptr(q), q.numel(), _dptr(out),
+                                                    _stream(stream)))
+    return out
+
+
+def mlp_gradients(params, q, target, stream=None):
+    torch = _torch()
+    grad = torch.empty(6337, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check("mbr_mlp_gradients", lib().mbr_mlp_gradients(_dptr(params), _dptr(q), _dptr(target),
+                                                        q.numel(), _dptr(grad), _dptr(loss),
+                                                        _stream(stream)))
+    return grad, loss
+
+
+def rank_batch(ranker: Ranker, q, out=None, stream=None):
+    """Ranks of the patterns in q (int32/int64 storage of uint32/uint64 patterns)
+    as an int32 tensor whose value -1 is MBR_NOT_FOUND."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(q.numel(), dtype=torch.int32, device="cuda")
+    _check("mbr_rank_batch", lib().mbr_rank_batch(ranker.handle, _dptr(q), q.numel(), _dptr(out),
+                                                  _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------------------- Hamiltonian
+class Hubbard:
+    def __init__(self, handle, precision: int, n_sectors: int):
+        self._h = handle
+        self.precision = precision
+        self.n_sectors = n_sectors
+        tot = C.c_uint64()
+        offs = (C.c_uint64 * (n_sectors + 1))()
+        _check("mbr_hubbard_dim", lib().mbr_hubbard_dim(self._h, C.byref(tot), offs))
+        self.dim = int(tot.value)
+        self.offsets = [int(v) for v in offs]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mbr_hubbard_destroy(self._h)
+            self._h = None
+
+
+def hubbard_create(L: int, bonds, sectors, U=None, eps=None, precision: int = F64, k: int = 0,
+                   stream=None) -> Hubbard:
+    """bonds: [(i, j, t)]; sectors: [(n_up, n_dn)]; U, eps: per-site lists or None."""
+    b = (Bond * max(1, len(bonds)))(*[Bond(int(i), int(j), float(t)) for i, j, t in bonds])
+    s = (SpinSector * len(sectors))(*[SpinSector(int(u), int(d)) for u, d in sectors])
+    Uv = (C.c_double * L)(*[float(u) for u in U]) if U is not None else None
+    ev = (C.c_double * L)(*[float(e) for e in eps]) if eps is not None else None
+    d = HubbardDesc(L=L, n_bonds=len(bonds), bonds=b, eps=ev, U=Uv, n_sectors=len(sectors),
+                    sectors=s, precision=precision, k=k)
+    h = C.c_void_p()
+    _check("mbr_hubbard_create", lib().mbr_hubbard_create(C.byref(d), C.byref(h), _stream(stream)))
+    return Hubbard(h, precision, len(sectors))
+
+
+def hubbard_apply(h: Hubbard, x, y, stream=None):
+    _check("mbr_hubbard_apply", lib().mbr_hubbard_apply(h.handle, _dptr(x), _dptr(y), _stream(stream)))
+    return y
+
+
+# --------------------------------------------------------------------------- Lanczos
+class Lanczos:
+    def __init__(self, handle, h: Hubbard, max_steps: int):
+        self._h = handle
+        self.ham = h
+        self.max_steps = max_steps
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mbr_lanczos_destroy(self._h)
+            self._h = None
+
+
+def lanczos_create(h: Hubbard, max_steps: int, reorth: bool = False, batched: bool = True,
+                   use_graph: bool = True, breakdown_tol: float = 0.0) -> Lanczos:
+    o = LanczosOpts(max_steps, int(reorth), int(batched), int(use_graph), breakdown_tol)
+    p = C.c_void_p()
+    _check("mbr_lanczos_create", lib().mbr_lanczos_create(h.handle, C.byref(o), C.byref(p)))
+    return Lanczos(p, h, max_steps)
+
+
+def lanczos_start(lz: Lanczos, v0, stream=None):
+    _check("mbr_lanczos_start", lib().mbr_lanczos_start(lz.handle, _dptr(v0), _stream(stream)))
+
+
+def lanczos_step(lz: Lanczos, nsteps: int, stream=None):
+    _check("mbr_lanczos_step", lib().mbr_lanczos_step(lz.handle, nsteps, _stream(stream)))
+
+
+def lanczos_result(lz: Lanczos, stream=None):
+    n = lz.ham.n_sectors
+    e0 = np.zeros(n)
+    steps = np.zeros(n, dtype=np.int32)
+    _check("mbr_lanczos_result", lib().mbr_lanczos_result(lz.handle, C.c_void_p(e0.ctypes.data),
+                                                          C.c_void_p(steps.ctypes.data),
+                                                          _stream(stream)))
+    return e0, steps
+
+
+def lanczos_coeffs(lz: Lanczos, stream=None):
+    n = lz.ham.n_sectors * lz.max_steps
+    a = np.zeros(n)
+    b = np.zeros(n)
+    _check("mbr_lanczos_coeffs", lib().mbr_lanczos_coeffs(lz.handle, C.c_void_p(a.ctypes.data),
+                                                          C.c_void_p(b.ctypes.data),
+                                                          _stream(stream)))
+    return a.reshape(lz.ham.n_sectors, -1), b.reshape(lz.ham.n_sectors, -1)
+
+
+def tridiag_lowest(alpha, beta, lengths, ld: int, out=None, stream=None):
+    torch = _torch()
+    nb = lengths.numel()
+    if out is None:
+        out = torch.empty(nb, dtype=torch.float64, device="cuda")
+    _check("mbr_tridiag_lowest", lib().mbr_tridiag_lowest(_dptr(alpha), _dptr(beta), _dptr(lengths),
+                                                          ld, nb, _dptr(out), _stream(stream)))
+    return out
+
+
+def declared_symbols():
+    """Names of every function declared in include/mbrank.h."""
+    import re
+    hdr = os.path.join(_HERE, "..", "include", "mbrank.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:const char \*|mbr_status|int32_t)\s*(mbr_\w+)\(", text,
+                                 re.M)))

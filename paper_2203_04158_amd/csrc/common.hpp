@@ -1,0 +1,151 @@
+// Internal declarations shared by the mbrank translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mbrank.h"
+
+namespace mbr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define MBR_FAIL(code, ...)          \
+    do {                             \
+        ::mbr::set_error(__VA_ARGS__); \
+        return (code);               \
+    } while (0)
+
+#define MBR_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            ::mbr::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                   \
+            return MBR_EHIP;                                                        \
+        }                                                                           \
+    } while (0)
+
+#define MBR_TRY(expr)                 \
+    do {                              \
+        mbr_status s_ = (expr);       \
+        if (s_ != MBR_OK) return s_;  \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- device buffer
+// Owning device allocation used by handles (tables, lists, work space).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    mbr_status alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? MBR_ENOMEM : MBR_EHIP;
+        }
+        bytes = n;
+        return MBR_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Allocate and fill from host synchronously on `stream`.
+mbr_status upload(DevBuf &b, const void *host, size_t bytes, hipStream_t stream);
+
+// ---------------------------------------------------------------- binomials
+// Exact C(n, k) for 0 <= n, k <= 64 (0 when k > n), host side.
+uint64_t binom(int n, int k);
+
+// Device copy of the same table (65 x 65 uint64, row n, column k) on the
+// current device; uploaded on first use and kept until the process ends.
+mbr_status device_binom(const uint64_t **d_table);
+
+// ---------------------------------------------------------------- handles
+struct mbr_sector_impl;
+int device_cu_count();
+
+// Launch geometry helper: number of workgroups for a grid-stride kernel.
+inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned max_blocks) {
+    uint64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return static_cast<unsigned>(b);
+}
+
+}  // namespace mbr
+
+// Opaque handle definitions (C-ABI names).
+struct mbr_sector {
+    int32_t M = 0;
+    int32_t width_bits = 32;
+    uint64_t n = 0;
+    int device = 0;
+    std::vector<mbr_popc_cons> cons;
+    mbr::DevBuf states;
+};
+
+// Staggered table description, shared by the staggered, spin and Hubbard paths.
+struct StagTable {
+    int32_t M = 0, k = 0, nmax = 0, nch = 0;
+    int32_t entry_bytes = 4;  // 2, 4 or 8
+    int32_t rowoff[65] = {0};  // row index of (chunk c, N' = 0)
+    int32_t nrows = 0;
+    mbr::DevBuf table;         // nrows << k entries
+    std::vector<uint64_t> host; // same entries as uint64
+};
+
+mbr_status stag_build(StagTable &t, int32_t M, int32_t k, int32_t nmax, int32_t entry_bytes,
+                      hipStream_t stream);
+
+struct TrieLevels;
+struct LearnedModel;
+
+struct mbr_ranker {
+    int32_t kind = 0;
+    int32_t M = 0, k = 0, width_bits = 32;
+    int32_t N = -1;            // staggered: particle number or -1
+    int32_t n_up = 0, n_dn = 0, L = 0;  // spin ranker
+    uint64_t n_states = 0;
+    int device = 0;
+    StagTable stag;            // staggered, spin halves
+    TrieLevels *trie = nullptr;
+    LearnedModel *learned = nullptr;
+    const mbr_sector *sector = nullptr;
+    const mbr_ranker *fallback = nullptr;
+    ~mbr_ranker();
+};
+
+// Per-kind rank launchers (defined in their translation units).
+mbr_status rank_staggered_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                                 hipStream_t s);
+mbr_status rank_spin_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                            hipStream_t s);
+mbr_status rank_trie_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                            hipStream_t s);
+mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                               hipStream_t s);
+void trie_free(TrieLevels *t);
+uint64_t trie_bytes(const TrieLevels *t);
+int32_t trie_levels(const TrieLevels *t);
+void learned_free(LearnedModel *m);
+uint64_t learned_bytes(const LearnedModel *m);

@@ -1,0 +1,377 @@
+// Staggered lookup (Sec. III.B): partial-rank tables and the rank kernels for
+// particle-number sectors and for spin-resolved sectors (Eq. rankupdown).
+//
+// Table layout: one row per (chunk c, N'), rows of chunk c start at rowoff[c],
+// 2^k entries per row with the chunk value fastest (the layout the paper
+// recommends so that only the rows a query touches are loaded).  A workgroup
+// copies the whole table into LDS once and then ranks a grid-stride share of
+// the queries: per query, ceil(M/k) dependent LDS reads and popcounts.
+#include "common.hpp"
+
+// ------------------------------------------------------------------ tables
+
+mbr_status stag_build(StagTable &t, int32_t M, int32_t k, int32_t nmax, int32_t entry_bytes,
+                      hipStream_t stream) {
+    using namespace mbr;
+    t.M = M;
+    t.k = k;
+    t.nmax = nmax;
+    t.nch = (M + k - 1) / k;
+    t.entry_bytes = entry_bytes;
+    int rows = 0;
+    for (int c = 0; c < t.nch; ++c) {
+        t.rowoff[c] = rows;
+        int Mp = c * k;
+        rows += (Mp < nmax ? Mp : nmax) + 1;
+    }
+    t.nrows = rows;
+    const uint64_t width = 1ull << k;
+    t.host.assign((uint64_t)rows * width, 0);
+    // Entry for (c, N', r), Eq. partrank evaluated through Eq. reuse: the
+    // combinadics rank of the chunk placed at offset M' above N' set bits,
+    // minus nothing (the N' low bits contribute C(j, j+1) = 0).
+    for (int c = 0; c < t.nch; ++c) {
+        int Mp = c * k;
+        int w = (M - Mp < k) ? (M - Mp) : k;
+        for (int Np = 0; Np <= (Mp < nmax ? Mp : nmax); ++Np) {
+            uint64_t *row = &t.host[(uint64_t)(t.rowoff[c] + Np) * width];
+            for (uint64_t r = 0; r < (1ull << w); ++r) {
+                uint64_t s = 0;
+                int q = Np + 1;
+                for (int b = 0; b < w; ++b)
+                    if ((r >> b) & 1) s += binom(Mp + b, q++);
+                row[r] = s;
+            }
+        }
+    }
+    // Entry width: at least the requested one, widened until the largest
+    // stored partial rank fits (rows never reached by a valid query included).
+    uint64_t maxv = 0;
+    for (uint64_t v : t.host) maxv = v > maxv ? v : maxv;
+    if (entry_bytes < 4 && maxv > 0xFFFFull) entry_bytes = 4;
+    if (entry_bytes < 8 && maxv > 0xFFFFFFFFull) entry_bytes = 8;
+    t.entry_bytes = entry_bytes;
+    size_t n = t.host.size();
+    if (entry_bytes == 8) return upload(t.table, t.host.data(), n * 8, stream);
+    if (entry_bytes == 4) {
+        std::vector<uint32_t> v(t.host.begin(), t.host.end());
+        return upload(t.table, v.data(), n * 4, stream);
+    }
+    std::vector<uint16_t> v(t.host.begin(), t.host.end());
+    return upload(t.table, v.data(), n * 2, stream);
+}
+
+namespace {
+
+// Smallest entry width (bytes) holding every partial rank of a table whose
+// ranks stay below C(M, nmax-ish): the largest entry is below max_N C(M, N').
+int entry_bytes_for(int M, int nmax) {
+    uint64_t mx = 0;
+    for (int n = 0; n <= nmax && n <= M; ++n) {
+        uint64_t b = mbr::binom(M, n);
+        mx = b > mx ? b : mx;
+    }
+    if (mx <= 0xFFFFull) return 2;
+    if (mx <= 0xFFFFFFFFull) return 4;
+    return 8;
+}
+
+struct StagArgs {
+    int32_t M, k, nch, N;
+    int32_t rowoff[16];
+    uint64_t nentries;
+};
+
+constexpr unsigned kBlock = 256;
+constexpr int kPerThread = 4;
+
+template <class P>
+__device__ __forceinline__ bool below_width(P x, int M) {
+    return (M >= (int)(8 * sizeof(P))) ? true : (x >> M) == 0;
+}
+
+// Rank of the low `bits` bits of x within its own particle-number block,
+// Fig. fastrank: add the partial rank of each k-bit chunk, advancing N' by
+// the chunk's popcount.  `tab` is the LDS copy of the table.
+template <class P, class E>
+__device__ __forceinline__ uint64_t stag_rank(P x, const E *tab, const StagArgs &a) {
+    uint64_t rank = 0;
+    int np = 0;
+    const P cm = (P)((1ull << a.k) - 1);
+#pragma unroll 4
+    for (int c = 0; c < a.nch; ++c) {
+        P r = (x >> (c * a.k)) & cm;
+        rank += (uint64_t)tab[((uint32_t)(a.rowoff[c] + np) << a.k) + (uint32_t)r];
+        np += (sizeof(P) == 8) ? __popcll((uint64_t)r) : __popc((uint32_t)r);
+    }
+    return rank;
+}
+
+template <class E>
+__device__ __forceinline__ void load_table(E *lds, const E *__restrict__ g, uint64_t n) {
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+    __syncthreads();
+}
+
+// USE_LDS = false reads the table through the caches instead (tables larger
+// than the LDS budget, e.g. k = 16 or 64-bit patterns with wide chunks).
+template <class P, class E, bool USE_LDS>
+__global__ void __launch_bounds__(kBlock) rank_staggered_kernel(const P *__restrict__ q, uint64_t n,
+                                                                uint32_t *__restrict__ out,
+                                                                const E *__restrict__ gtab,
+                                                                StagArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const E *tab = gtab;
+    if constexpr (USE_LDS) {
+        E *t = reinterpret_cast<E *>(lds_raw);
+        load_table(t, gtab, a.nentries);
+        tab = t;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; base < n;
+         base += stride * kPerThread) {
+        P x[kPerThread];
+        bool ok[kPerThread];
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            uint64_t j = base + u * stride;
+            x[u] = (j < n) ? q[j] : (P)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            int h = (sizeof(P) == 8) ? __popcll((uint64_t)x[u]) : __popc((uint32_t)x[u]);
+            ok[u] = below_width(x[u], a.M) && (a.N < 0 || h == a.N);
+            if (!ok[u]) x[u] = 0;  // keeps every table row in range
+        }
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            uint64_t j = base + u * stride;
+            uint64_t r = stag_rank<P, E>(x[u], tab, a);
+            if (j < n) out[j] = ok[u] ? (uint32_t)r : MBR_NOT_FOUND;
+        }
+    }
+}
+
+struct SpinArgs {
+    StagArgs half;      // table over L-bit halves (universal up to nmax)
+    int32_t L, n_up, n_dn;
+    uint32_t mult;      // C(L, n_dn)
+};
+
+template <class P, class E, bool USE_LDS>
+__global__ void __launch_bounds__(kBlock) rank_spin_kernel(const P *__restrict__ q, uint64_t n,
+                                                           uint32_t *__restrict__ out,
+                                                           const E *__restrict__ gtab, SpinArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const E *tab = gtab;
+    if constexpr (USE_LDS) {
+        E *t = reinterpret_cast<E *>(lds_raw);
+        load_table(t, gtab, a.half.nentries);
+        tab = t;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const P hm = (P)((a.L >= 32 && sizeof(P) == 8) ? 0xFFFFFFFFull : ((1ull << a.L) - 1));
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
+        P x = q[j];
+        P dn = x & hm;
+        P up = (x >> a.L) & hm;
+        int hd = (sizeof(P) == 8) ? __popcll((uint64_t)dn) : __popc((uint32_t)dn);
+        int hu = (sizeof(P) == 8) ? __popcll((uint64_t)up) : __popc((uint32_t)up);
+        bool ok = below_width(x, 2 * a.L) && hd == a.n_dn && hu == a.n_up;
+        if (!ok) { dn = 0; up = 0; }
+        uint64_t rd = stag_rank<P, E>(dn, tab, a.half);
+        uint64_t ru = stag_rank<P, E>(up, tab, a.half);
+        out[j] = ok ? (uint32_t)(ru * a.mult + rd) : MBR_NOT_FOUND;
+    }
+}
+
+StagArgs make_args(const StagTable &t, int N) {
+    StagArgs a{};
+    a.M = t.M;
+    a.k = t.k;
+    a.nch = t.nch;
+    a.N = N;
+    for (int c = 0; c < t.nch && c < 16; ++c) a.rowoff[c] = t.rowoff[c];
+    a.nentries = (uint64_t)t.nrows << t.k;
+    return a;
+}
+
+// Tables up to this size are staged in LDS (several workgroups per CU still fit).
+constexpr size_t kLdsTable = 64 * 1024;
+
+template <class K>
+mbr_status set_lds(K kernel, size_t bytes) {
+    if (bytes > 64 * 1024)
+        MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return MBR_OK;
+}
+
+template <class P, class E>
+mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                       hipStream_t s) {
+    StagArgs a = make_args(r->stag, r->N);
+    size_t lds = a.nentries * sizeof(E);
+    unsigned grid = mbr::grid_for(n, kBlock * kPerThread, mbr::device_cu_count() * 4);
+    if (lds <= kLdsTable) {
+        auto kern = rank_staggered_kernel<P, E, true>;
+        MBR_TRY(set_lds(kern, lds));
+        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
+    } else {
+        rank_staggered_kernel<P, E, false><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
+                                                                  r->stag.table.as<E>(), a);
+    }
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+template <class P, class E>
+mbr_status launch_spin(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                       hipStream_t s) {
+    SpinArgs a{};
+    a.half = make_args(r->stag, -1);
+    a.L = r->L;
+    a.n_up = r->n_up;
+    a.n_dn = r->n_dn;
+    a.mult = (uint32_t)mbr::binom(r->L, r->n_dn);
+    size_t lds = a.half.nentries * sizeof(E);
+    unsigned grid = mbr::grid_for(n, kBlock, mbr::device_cu_count() * 8);
+    if (lds <= kLdsTable) {
+        auto kern = rank_spin_kernel<P, E, true>;
+        MBR_TRY(set_lds(kern, lds));
+        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
+    } else {
+        rank_spin_kernel<P, E, false><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
+                                                             r->stag.table.as<E>(), a);
+    }
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+}  // namespace
+
+mbr_status rank_staggered_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                                 hipStream_t s) {
+    int eb = r->stag.entry_bytes;
+    if (r->width_bits == 32) {
+        if (eb == 2) return launch_stag<uint32_t, uint16_t>(r, q, n, out, s);
+        if (eb == 4) return launch_stag<uint32_t, uint32_t>(r, q, n, out, s);
+        return launch_stag<uint32_t, uint64_t>(r, q, n, out, s);
+    }
+    if (eb == 2) return launch_stag<uint64_t, uint16_t>(r, q, n, out, s);
+    if (eb == 4) return launch_stag<uint64_t, uint32_t>(r, q, n, out, s);
+    return launch_stag<uint64_t, uint64_t>(r, q, n, out, s);
+}
+
+mbr_status rank_spin_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                            hipStream_t s) {
+    int eb = r->stag.entry_bytes;
+    if (r->width_bits == 32) {
+        if (eb == 2) return launch_spin<uint32_t, uint16_t>(r, q, n, out, s);
+        if (eb == 4) return launch_spin<uint32_t, uint32_t>(r, q, n, out, s);
+        return launch_spin<uint32_t, uint64_t>(r, q, n, out, s);
+    }
+    if (eb == 2) return launch_spin<uint64_t, uint16_t>(r, q, n, out, s);
+    if (eb == 4) return launch_spin<uint64_t, uint32_t>(r, q, n, out, s);
+    return launch_spin<uint64_t, uint64_t>(r, q, n, out, s);
+}
+
+#define MBR_FAIL_DEL(obj, code, ...) \
+    do {                             \
+        delete (obj);                \
+        MBR_FAIL(code, __VA_ARGS__); \
+    } while (0)
+
+extern "C" {
+
+mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t width_bits,
+                                      mbr_ranker **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (M < 1 || M > 64) MBR_FAIL(MBR_EINVAL, "M=%d outside 1..64", M);
+    if (k < 1 || k > 16) MBR_FAIL(MBR_EINVAL, "k=%d outside 1..16", k);
+    if (width_bits != 32 && width_bits != 64) MBR_FAIL(MBR_EINVAL, "width_bits=%d", width_bits);
+    if (width_bits == 32 && M > 32) MBR_FAIL(MBR_EINVAL, "M=%d needs 64-bit patterns", M);
+    if (N < -1 || N > M) MBR_FAIL(MBR_EINVAL, "N=%d outside -1..M", N);
+    int nch = (M + k - 1) / k;
+    if (nch > 16) MBR_FAIL(MBR_EUNSUPPORTED, "%d chunks (at most 16)", nch);
+    int nmax = N < 0 ? M : N;
+    uint64_t worst = 0;
+    for (int n = (N < 0 ? 0 : N); n <= (N < 0 ? M : N); ++n) worst = binom(M, n) > worst ? binom(M, n) : worst;
+    if (worst >= 0xFFFFFFFFull) MBR_FAIL(MBR_ERANGE, "ranks up to %llu do not fit 32 bits", (unsigned long long)worst);
+    auto *r = new (std::nothrow) mbr_ranker;
+    if (!r) MBR_FAIL(MBR_ENOMEM, "host allocation");
+    r->kind = MBR_RANKER_STAGGERED;
+    r->M = M;
+    r->k = k;
+    r->N = N;
+    r->width_bits = width_bits;
+    r->n_states = N < 0 ? ((M >= 64) ? ~0ull : (1ull << M)) : binom(M, N);
+    (void)hipGetDevice(&r->device);
+    if (((uint64_t)(nch * (nmax + 1)) << k) > (1ull << 26))
+        MBR_FAIL_DEL(r, MBR_EUNSUPPORTED, "staggered table beyond 2^26 entries");
+    mbr_status st = stag_build(r->stag, M, k, nmax, entry_bytes_for(M, nmax), as_stream(stream));
+    if (st != MBR_OK) {
+        delete r;
+        return st;
+    }
+    *out = r;
+    return MBR_OK;
+}
+
+mbr_status mbr_staggered_table_copy(const mbr_ranker *r, uint64_t *host_out, uint64_t cap,
+                                    uint64_t *n_entries, void *stream) {
+    (void)stream;
+    if (!r) MBR_FAIL(MBR_EINVAL, "null ranker");
+    if (r->kind != MBR_RANKER_STAGGERED && r->kind != MBR_RANKER_SPIN)
+        MBR_FAIL(MBR_EINVAL, "not a staggered or spin ranker");
+    uint64_t n = (uint64_t)r->stag.nrows << r->stag.k;
+    if (n_entries) *n_entries = n;
+    if (!host_out || cap < n) return MBR_OK;
+    // Read back what the device holds, widened to uint64.
+    size_t eb = r->stag.entry_bytes;
+    std::vector<unsigned char> raw(n * eb);
+    MBR_HIP(hipMemcpy(raw.data(), r->stag.table.p, n * eb, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        if (eb == 2) host_out[i] = reinterpret_cast<uint16_t *>(raw.data())[i];
+        else if (eb == 4) host_out[i] = reinterpret_cast<uint32_t *>(raw.data())[i];
+        else host_out[i] = reinterpret_cast<uint64_t *>(raw.data())[i];
+    }
+    return MBR_OK;
+}
+
+mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t k,
+                                 mbr_ranker **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (L < 1 || L > 32) MBR_FAIL(MBR_EINVAL, "L=%d outside 1..32", L);
+    if (n_up < 0 || n_up > L || n_dn < 0 || n_dn > L) MBR_FAIL(MBR_EINVAL, "particle numbers (%d,%d)", n_up, n_dn);
+    if (k < 1 || k > 16) MBR_FAIL(MBR_EINVAL, "k=%d outside 1..16", k);
+    uint64_t total = binom(L, n_up) * binom(L, n_dn);
+    if (total >= 0xFFFFFFFFull) MBR_FAIL(MBR_ERANGE, "spin sector of %llu states", (unsigned long long)total);
+    auto *r = new (std::nothrow) mbr_ranker;
+    if (!r) MBR_FAIL(MBR_ENOMEM, "host allocation");
+    r->kind = MBR_RANKER_SPIN;
+    r->M = 2 * L;
+    r->L = L;
+    r->k = k;
+    r->n_up = n_up;
+    r->n_dn = n_dn;
+    r->width_bits = (2 * L <= 32) ? 32 : 64;
+    r->n_states = total;
+    (void)hipGetDevice(&r->device);
+    int nmax = n_up > n_dn ? n_up : n_dn;
+    int eb = entry_bytes_for(L, nmax);
+    if ((L + k - 1) / k > 16) MBR_FAIL_DEL(r, MBR_EUNSUPPORTED, "more than 16 chunks");
+    mbr_status st = stag_build(r->stag, L, k, nmax, eb, as_stream(stream));
+    if (st != MBR_OK) {
+        delete r;
+        return st;
+    }
+    *out = r;
+    return MBR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""GPU parity of sector enumeration, unrank, staggered and spin-resolved ranking
+against the oracle (bit-exact)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import combinatorics as OC
+from oracle import staggered as OS
+import synth
+from tests._util import dev_u32, dev_u64, host_u32, host_u64, host_rank, say
+
+pytestmark = pytest.mark.gpu
+
+mbr = pytest.importorskip("paper_2203_04158_amd")
+
+
+def _build(M, cons, width=32):
+    return mbr.sector_build(M, cons, width_bits=width)
+
+
+@pytest.mark.parametrize("M,cons", [
+    (4, OC.constraints(4, 3)),
+    (12, OC.constraints(12, 5)),
+    (24, OC.constraints(24, 12)),
+    (20, [(0xFF, 2, 5), (0xF0000, 1, 1)]),          # no fixed N: full scan
+    (16, OC.constraints(16, 8, [(0xF, 3, 4)])),      # RAS-like
+    (28, OC.spin_constraints(14, 7, 7)),             # spin product via disjoint windows
+    (10, [((1 << 10) - 1, 4, 4), (0x3, 3, 3)]),      # empty sector
+    (1, OC.constraints(1, 1)),
+])
+def test_sector_build(M, cons):
+    say("sector", M, cons)
+    want = OC.sector_enumerate(M, cons)
+    s = _build(M, cons)
+    assert s.size == want.size
+    if want.size:
+        assert np.array_equal(host_u32(s.states()), want)
+
+
+def test_sector_build_u64():
+    cons = OC.constraints(36, 3, [(0x7, 1, 2)])
+    want = OC.sector_enumerate(36, cons)
+    s = _build(36, cons, width=64)
+    assert s.size == want.size
+    assert np.array_equal(host_u64(s.states()), want)
+
+
+def test_unrank_edges():
+    s = _build(12, OC.constraints(12, 6))
+    st = OC.sector_enumerate(12, OC.constraints(12, 6))
+    idx = np.array([0, 1, st.size - 1, st.size, 2 ** 31, 0xFFFFFFFE], dtype=np.uint64)
+    got = host_u32(mbr.unrank_batch(s, dev_u32(idx)))
+    assert list(got[:3]) == [st[0], st[1], st[-1]]
+    assert (got[3:] == 0xFFFFFFFF).all()
+    import torch
+    empty = torch.empty(0, dtype=torch.int32, device="cuda")
+    assert mbr.unrank_batch(s, empty).numel() == 0
+
+
+@pytest.mark.parametrize("M,N,k", [(24, 12, 8), (13, 6, 5), (32, 16, 8), (14, -1, 7), (9, 3, 16)])
+def test_staggered_table_entries(M, N, k):
+    r = mbr.build_staggered_tables(M, N, k)
+    tab = mbr.staggered_table(r)
+    nmax = M if N < 0 else N
+    rows = OS.staggered_rows(M, k, nmax)
+    assert tab.size == len(rows) << k
+    for ri, (c, Mp, Np, w) in enumerate(rows):
+        for v in range(1 << w):
+            assert tab[(ri << k) + v] == OS.partrank(v, Mp, Np)
+
+
+def test_staggered_cfg1_all_members_and_queries():
+    M, N, k = 24, 12, 8
+    st = OC.sector_enumerate(M, OC.constraints(M, N))
+    r = mbr.build_staggered_tables(M, N, k)
+    got = host_rank(mbr.rank_batch(r, dev_u32(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    # 2^22 seeded uniform queries, as in the ranking microbenchmark
+    idx = synth.uniform_indices(1, 1 << 22, st.size)
+    q = st[idx]
+    got = host_rank(mbr.rank_batch(r, dev_u32(q)))
+    assert np.array_equal(got, OC.bisect_rank(st, q))
+    # non-members: wrong popcount, bits at or above M
+    bad = np.concatenate([synth.splitmix64(5, 100000) & np.uint64(0xFFFFFFFF),
+                          st[:1000] | np.uint64(1 << 24)])
+    got = host_rank(mbr.rank_batch(r, dev_u32(bad)))
+    assert np.array_equal(got, OC.bisect_rank(st, bad))
+
+
+@pytest.mark.parametrize("M,N,k", [(13, 6, 1), (13, 6, 3), (17, 9, 5), (20, 3, 11), (32, 16, 16),
+                                   (32, 1, 8), (32, 31, 4), (16, 0, 8), (16, 16, 8)])
+def test_staggered_against_cns(M, N, k):
+    q = synth.random_subset_patterns(M * 100 + N, 50000, M, N)
+    noise = synth.splitmix64(M + 7 * N, 20000) & np.uint64((1 << M) - 1)
+    q = np.concatenate([q, noise])
+    r = mbr.build_staggered_tables(M, N, k)
+    got = host_rank(mbr.rank_batch(r, dev_u32(q)))
+    pc = np.array([bin(int(a)).count("1") for a in q])
+    want = np.where(pc == N, OC.cns_rank_batch(q).astype(np.int64), -1)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("M,N,k", [(40, 20, 8), (64, 32, 8), (64, 5, 13), (48, 24, 16)])
+def test_staggered_u64(M, N, k):
+    q = synth.random_subset_patterns(M + N + k, 40000, M, N)
+    if math.comb(M, N) >= 2 ** 32 - 1:
+        with pytest.raises(mbr.MbrError):
+            mbr.build_staggered_tables(M, N, k, width_bits=64)
+        return
+    r = mbr.build_staggered_tables(M, N, k, width_bits=64)
+    got = host_rank(mbr.rank_batch(r, dev_u64(q)))
+    assert np.array_equal(got, OC.cns_rank_batch(q).astype(np.int64))
+
+
+@pytest.mark.parametrize("L,nu,nd,k", [(14, 7, 7, 7), (14, 7, 7, 14), (12, 3, 8, 5), (4, 1, 2, 2),
+                                       (12, 0, 12, 6), (16, 4, 5, 8)])
+def test_spin_ranker(L, nu, nd, k):
+    st = OC.sector_enumerate(2 * L, OC.spin_constraints(L, nu, nd))
+    r = mbr.build_spin_ranker(L, nu, nd, k)
+    got = host_rank(mbr.rank_batch(r, dev_u32(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    bad = synth.splitmix64(L * 31 + nu, 50000) & np.uint64((1 << min(32, 2 * L + 1)) - 1)
+    got = host_rank(mbr.rank_batch(r, dev_u32(bad)))
+    assert np.array_equal(got, OC.bisect_rank(st, bad))
