@@ -66,18 +66,20 @@ def sector(L: int, n_up: int, n_dn: int) -> np.ndarray:
     return sector_enumerate(2 * L, spin_constraints(L, n_up, n_dn))
 
 
-def apply(states, tl, x, rows=None, with_abssum: bool = False):
-    """y[rows] = (H x)[rows] by Eq. Talpha2 over the term list."""
+def apply(states, tl, x, rows=None, with_abssum: bool = False, row_range=None):
+    """y[rows] = (H x)[rows] by Eq. Talpha2 over the term list; row_range=(a, b)
+    restricts the product to the contiguous rows a..b-1."""
     states = np.ascontiguousarray(states, dtype=np.uint64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     v, m, l, r, xx, s = _arrays(tl)
     L = lib()
     if rows is None:
-        y = np.empty(states.size)
-        a = np.empty(states.size) if with_abssum else None
+        r0, r1 = row_range if row_range is not None else (0, states.size)
+        y = np.empty(r1 - r0)
+        a = np.empty(r1 - r0) if with_abssum else None
         rc = L.orc_apply_terms_bra(ptr(states), states.size, len(tl), ptr(v), ptr(m), ptr(l),
                                    ptr(xx), ptr(s), ptr(x), ptr(y),
-                                   ptr(a) if a is not None else None, 0, states.size)
+                                   ptr(a) if a is not None else None, r0, r1)
         if rc != 0:
             raise ValueError(f"term leaves the sector at row {-rc - 1}")
         return (y, a) if with_abssum else y

@@ -1,0 +1,636 @@
+// Lanczos ground-state search per (N_up, N_dn) sector on the on-the-fly H·x,
+// and the lowest eigenvalue of the tridiagonal matrices by Sturm bisection.
+//
+// Recurrence per sector: u = H v_j - beta_{j-1} v_{j-1}; alpha_j = <v_j, u>;
+// w = u - alpha_j v_j; [full classical Gram-Schmidt of w against v_1..v_j];
+// beta_j = |w|; v_{j+1} = w / beta_j.  All dot products accumulate in fp64 with
+// fixed-order reductions (per tile, then per sector), so runs are bitwise
+// repeatable.  Scalars live on the device and every kernel reads its step
+// index there, so a step is a fixed launch sequence that can be captured once
+// into a hipGraph and replayed; the host never waits inside a step.
+//
+// Plain path (no reorthogonalisation): two vectors only.  The stored q_j are
+// unnormalised (q_{j+1} = w) and v_j = s_j q_j with s_j = 1/beta_{j-1} is folded
+// into the kernels, so a step costs one H·x pass (which also forms u in place
+// over q_{j-1} and the <q_j, u> partials) and one update pass (w and |w|^2).
+// Reorthogonalising path: v_1..v_m are kept in the Hamiltonian's precision
+// (fp32 in the mixed form) for the Gram-Schmidt passes; coefficients are fp64.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "hubbard.hpp"
+
+using namespace mbr;
+
+namespace {
+
+constexpr unsigned kBlock = 256;
+constexpr int kRedWaves = kBlock / 64;
+
+struct LzDev {
+    double *alpha;   // [ns][m]
+    double *beta;    // [ns][m]
+    double *c1, *c2, *c3;  // per-sector step scalars
+    double *pd;      // per-slot dot partials
+    double *pn;      // per-slot norm partials
+    double *pc;      // per-slot Gram-Schmidt partials [slot][m+1]
+    double *cgs;     // per-sector Gram-Schmidt coefficients [ns][m+1]
+    double *norm0;   // per-sector start norms
+    int32_t *active; // per-sector flag
+    int32_t *steps;  // per-sector completed steps
+    int32_t *j;      // basis index of the current vector (reorthogonalising path)
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Fixed-order block sum; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+// Sum of n partials of one sector by one workgroup, fixed order.
+__device__ __forceinline__ double sector_sum(const double *p, uint32_t n, double *red) {
+    double v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return block_sum(v, red);
+}
+
+// alpha_j = c1 * sum(pd); c3 = alpha_j * c1 (coefficient of the stored q_j in w).
+__global__ void lz_alpha(const HvSector *secs, LzDev d, int m, uint32_t s_first) {
+    __shared__ double red[kRedWaves];
+    const uint32_t s = s_first + blockIdx.x;
+    if (!d.active[s]) return;
+    double sum = sector_sum(d.pd + secs[s].slot0, secs[s].nslots, red);
+    if (threadIdx.x == 0) {
+        double a = d.c1[s] * sum;
+        d.alpha[(size_t)s * m + d.steps[s]] = a;
+        d.c3[s] = a * d.c1[s];
+    }
+}
+
+// beta_j = sqrt(sum(pn)); the sector stops at breakdown, at its dimension or at
+// m steps; otherwise the scalars of the next step are prepared.
+__global__ void lz_beta(const HvSector *secs, LzDev d, int m, double tol, int reorth,
+                        uint32_t s_first) {
+    __shared__ double red[kRedWaves];
+    const uint32_t s = s_first + blockIdx.x;
+    if (!d.active[s]) return;
+    double sum = sector_sum(d.pn + secs[s].slot0, secs[s].nslots, red);
+    if (threadIdx.x == 0) {
+        const int j = d.steps[s];
+        const double b = sqrt(sum);
+        const double a = d.alpha[(size_t)s * m + j];
+        const double bprev = j > 0 ? d.beta[(size_t)s * m + j - 1] : 0.0;
+        const uint64_t dim = (uint64_t)secs[s].cup * secs[s].cdn;
+        const bool stop = (b <= tol * (fabs(a) + bprev)) || (uint64_t)(j + 1) >= dim || j + 1 >= m;
+        d.beta[(size_t)s * m + j] = stop ? 0.0 : b;
+        d.steps[s] = j + 1;
+        if (stop) {
+            d.active[s] = 0;
+        } else if (reorth) {
+            d.c1[s] = 1.0;
+            d.c2[s] = b;
+            d.c3[s] = 1.0 / b;
+        } else {
+            d.c2[s] = b * d.c1[s];
+            d.c1[s] = 1.0 / b;
+        }
+    }
+}
+
+// w = u - c3 q over a tile's rows (in place in u); partial |w|^2.
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_update(const HvTile *tiles, uint32_t n_tiles,
+                                                    const HvSector *secs, T *__restrict__ u,
+                                                    const T *__restrict__ q, LzDev d) {
+    __shared__ double red[kRedWaves];
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        const HvSector sc = secs[tl.sector];
+        if (!d.active[tl.sector]) {
+            if (threadIdx.x == 0) d.pn[tl.slot] = 0.0;
+            continue;
+        }
+        const T c = (T)d.c3[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        double acc = 0;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            T w = u[base + e] - c * q[base + e];
+            u[base + e] = w;
+            acc += (double)w * (double)w;
+        }
+        double s = block_sum(acc, red);
+        if (threadIdx.x == 0) d.pn[tl.slot] = s;
+    }
+}
+
+// Per-slot |v|^2 of a vector (start normalisation).
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_norm_parts(const HvTile *tiles, uint32_t n_tiles,
+                                                        const HvSector *secs, const T *__restrict__ v,
+                                                        double *parts) {
+    __shared__ double red[kRedWaves];
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        const HvSector sc = secs[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        double acc = 0;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            double w = (double)v[base + e];
+            acc += w * w;
+        }
+        double s = block_sum(acc, red);
+        if (threadIdx.x == 0) parts[tl.slot] = s;
+    }
+}
+
+__global__ void lz_start_scalars(const HvSector *secs, LzDev d, int reorth) {
+    __shared__ double red[kRedWaves];
+    const uint32_t s = blockIdx.x;
+    double sum = sector_sum(d.pn + secs[s].slot0, secs[s].nslots, red);
+    if (threadIdx.x == 0) {
+        double nrm = sqrt(sum);
+        d.norm0[s] = nrm;
+        d.active[s] = nrm > 0.0 ? 1 : 0;
+        d.steps[s] = 0;
+        d.c1[s] = reorth ? 1.0 : (nrm > 0 ? 1.0 / nrm : 0.0);
+        d.c2[s] = 0.0;
+        d.c3[s] = nrm > 0 ? 1.0 / nrm : 0.0;
+        if (s == 0) *d.j = 0;
+    }
+}
+
+template <class T>
+__global__ void lz_convert(const double *__restrict__ v0, T *__restrict__ out, uint64_t n) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (T)v0[i];
+}
+
+template <class T>
+__global__ void lz_fill_zero(T *__restrict__ out, uint64_t n) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (T)0;
+}
+
+// dst = c3 * w per sector.  With use_j the destination is basis vector j+1
+// (v_{j+1} = w / beta_j, only sectors still running); otherwise vector 0.
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_scale_into(const HvTile *tiles, uint32_t n_tiles,
+                                                        const HvSector *secs, const T *__restrict__ w,
+                                                        T *__restrict__ V, uint64_t total, LzDev d,
+                                                        int use_j) {
+    const int64_t j = use_j ? (int64_t)(*d.j) + 1 : 0;
+    T *dst = V + (uint64_t)j * total;
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        if (use_j && !d.active[tl.sector]) continue;
+        const HvSector sc = secs[tl.sector];
+        const T c = (T)d.c3[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) dst[base + e] = w[base + e] * c;
+    }
+}
+
+// Reorthogonalising path: w = u - c3 v_j in place, then per-slot partials of
+// <v_k, w> for k = 0..j (classical Gram-Schmidt coefficients).
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, uint32_t n_tiles,
+                                                         const HvSector *secs, T *__restrict__ W,
+                                                         const T *__restrict__ V, uint64_t total,
+                                                         int m, LzDev d) {
+    __shared__ double red[kRedWaves];
+    const int j = *d.j;
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        if (!d.active[tl.sector]) continue;
+        double *pc = d.pc + (size_t)tl.slot * (m + 1);
+        const HvSector sc = secs[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        const T c = (T)d.c3[tl.sector];
+        const T *vj = V + (uint64_t)j * total;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) W[base + e] = W[base + e] - c * vj[base + e];
+        __syncthreads();
+        for (int k = 0; k <= j; ++k) {
+            const T *vk = V + (uint64_t)k * total;
+            double acc = 0;
+            for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
+                acc += (double)vk[base + e] * (double)W[base + e];
+            double s = block_sum(acc, red);
+            if (threadIdx.x == 0) pc[k] = s;
+        }
+    }
+}
+
+__global__ void lz_reduce_cgs(const HvSector *secs, LzDev d, int m, uint32_t s_first) {
+    __shared__ double red[kRedWaves];
+    const uint32_t s = s_first + blockIdx.x;
+    if (!d.active[s]) return;
+    const int j = *d.j;
+    const HvSector sc = secs[s];
+    for (int k = 0; k <= j; ++k) {
+        double v = 0;
+        for (uint32_t i = threadIdx.x; i < sc.nslots; i += blockDim.x)
+            v += d.pc[(size_t)(sc.slot0 + i) * (m + 1) + k];
+        double t = block_sum(v, red);
+        if (threadIdx.x == 0) d.cgs[(size_t)s * (m + 1) + k] = t;
+    }
+}
+
+// w -= sum_k c_k v_k (fp64 accumulation), then partial |w|^2.
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_subtract(const HvTile *tiles, uint32_t n_tiles,
+                                                      const HvSector *secs, T *__restrict__ W,
+                                                      const T *__restrict__ V, uint64_t total, int m,
+                                                      LzDev d) {
+    __shared__ double red[kRedWaves];
+    const int j = *d.j;
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        if (!d.active[tl.sector]) {
+            if (threadIdx.x == 0) d.pn[tl.slot] = 0.0;
+            continue;
+        }
+        const HvSector sc = secs[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        const double *c = d.cgs + (size_t)tl.sector * (m + 1);
+        double acc = 0;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            double w = (double)W[base + e];
+            for (int k = 0; k <= j; ++k) w -= c[k] * (double)V[(uint64_t)k * total + base + e];
+            T wt = (T)w;
+            W[base + e] = wt;
+            acc += (double)wt * (double)wt;
+        }
+        double s = block_sum(acc, red);
+        if (threadIdx.x == 0) d.pn[tl.slot] = s;
+    }
+}
+
+__global__ void lz_advance(LzDev d, int m) {
+    if (*d.j < m) *d.j += 1;
+}
+
+// ---------------------------------------------------------------- tridiagonal
+// Number of eigenvalues below x: negative pivots of the LDL^T factorisation of
+// T - x I (Sturm sequence).
+__device__ __forceinline__ int sturm_count(const double *a, const double *b, int n, double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+        const double qq = (q == 0.0) ? -1e-300 : q;
+        q = (a[i] - x) - b[i - 1] * b[i - 1] / qq;
+        if (q < 0) ++c;
+    }
+    return c;
+}
+
+// One wave per matrix: 64-way multisection of the Gershgorin interval, keeping
+// the sub-interval where the Sturm count first reaches one.
+__global__ void tridiag_lowest_kernel(const double *alpha, const double *beta, const int32_t *len,
+                                      int ld, int nb, double *e0) {
+    const int bi = blockIdx.x;
+    if (bi >= nb) return;
+    const int lane = threadIdx.x;
+    int n = len[bi];
+    if (n > ld) n = ld;
+    const double *a = alpha + (size_t)bi * ld;
+    const double *b = beta + (size_t)bi * ld;
+    if (n <= 0) {
+        if (lane == 0) e0[bi] = 0.0;
+        return;
+    }
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < n ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    const double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
+    lo -= pad;
+    hi += pad;
+    for (int it = 0; it < 40; ++it) {
+        if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+        const double h = (hi - lo) / 65.0;
+        const double x = lo + h * (double)(lane + 1);
+        const int c = sturm_count(a, b, n, x);
+        const unsigned long long ball = __ballot(c >= 1);
+        const int first = ball ? (__ffsll((long long)ball) - 1) : 64;
+        const double nlo = lo + h * (double)first;
+        const double nhi = (first == 64) ? hi : lo + h * (double)(first + 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) e0[bi] = 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- handle
+struct mbr_lanczos {
+    const mbr_hubbard *h = nullptr;
+    mbr_lanczos_opts o{};
+    int ns = 0, m = 0, prec = MBR_F64;
+    size_t tsz = 8;
+    uint64_t total = 0;
+    uint32_t n_slots = 0;
+    std::vector<HvSector> secs;
+    DevBuf d_tiles_slot, d_secs;
+    DevBuf bufA, bufB, basis, work;
+    DevBuf alpha, beta, c1, c2, c3, pd, pn, pc, cgs, norm0, active, steps, jcount, e0;
+    LzDev dev{};
+    int parity = 0;  // plain path: 0 -> q_j in A, 1 -> q_j in B
+    bool started = false;
+    unsigned grid = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;
+    ~mbr_lanczos() {
+        for (auto &g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+namespace {
+
+double default_tol(const mbr_lanczos *lz) {
+    if (lz->o.breakdown_tol > 0) return lz->o.breakdown_tol;
+    return lz->prec == MBR_F64 ? 1e-12 : 1e-6;
+}
+
+// Kernels of one step for sectors [s0, s0 + nsec) whose tiles are the slot
+// range [t0, t0 + nt).
+template <class T>
+mbr_status enqueue_plain(mbr_lanczos *lz, int par, uint32_t s0, uint32_t nsec, uint32_t t0,
+                         uint32_t nt, bool all, hipStream_t s) {
+    T *X = par ? lz->bufB.as<T>() : lz->bufA.as<T>();
+    T *P = par ? lz->bufA.as<T>() : lz->bufB.as<T>();
+    const HvSector *secs = lz->d_secs.as<HvSector>();
+    const HvTile *tiles = lz->d_tiles_slot.as<HvTile>() + t0;
+    HvEpilogue ep{};
+    ep.c1 = lz->dev.c1;
+    ep.c2 = lz->dev.c2;
+    ep.p = P;
+    ep.partial = lz->dev.pd;
+    ep.active = lz->dev.active;
+    if (!all) {
+        ep.tiles = tiles;
+        ep.n_tiles = nt;
+    }
+    MBR_TRY(hubbard_launch(lz->h, X, P, ep, s));
+    const unsigned g = std::min<unsigned>(lz->grid, nt);
+    lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
+    lz_update<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, P, X, lz->dev);
+    lz_beta<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, default_tol(lz), 0, s0);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+template <class T>
+mbr_status enqueue_reorth(mbr_lanczos *lz, uint32_t s0, uint32_t nsec, uint32_t t0, uint32_t nt,
+                          bool all, hipStream_t s) {
+    T *V = lz->basis.as<T>();
+    T *W = lz->work.as<T>();
+    const HvSector *secs = lz->d_secs.as<HvSector>();
+    const HvTile *tiles = lz->d_tiles_slot.as<HvTile>() + t0;
+    HvEpilogue ep{};
+    ep.c1 = lz->dev.c1;
+    ep.c2 = lz->dev.c2;
+    ep.p = V;
+    ep.partial = lz->dev.pd;
+    ep.active = lz->dev.active;
+    ep.basis_j = lz->dev.j;
+    ep.basis_stride = lz->total;
+    if (!all) {
+        ep.tiles = tiles;
+        ep.n_tiles = nt;
+    }
+    MBR_TRY(hubbard_launch(lz->h, V, W, ep, s));
+    const unsigned g = std::min<unsigned>(lz->grid, nt);
+    lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
+    lz_update_dots<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->m, lz->dev);
+    lz_reduce_cgs<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
+    lz_subtract<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->m, lz->dev);
+    lz_beta<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, default_tol(lz), 1, s0);
+    lz_scale_into<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->dev, 1);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+// One full step (all sectors), batched or one launch set per sector.
+template <class T>
+mbr_status enqueue_step(mbr_lanczos *lz, int par, hipStream_t s) {
+    const bool reorth = lz->o.reorth != 0;
+    if (lz->o.batched) {
+        if (reorth) MBR_TRY(enqueue_reorth<T>(lz, 0, lz->ns, 0, lz->n_slots, true, s));
+        else MBR_TRY(enqueue_plain<T>(lz, par, 0, lz->ns, 0, lz->n_slots, true, s));
+    } else {
+        for (int si = 0; si < lz->ns; ++si) {
+            const HvSector &sc = lz->secs[si];
+            if (reorth) MBR_TRY(enqueue_reorth<T>(lz, si, 1, sc.slot0, sc.nslots, false, s));
+            else MBR_TRY(enqueue_plain<T>(lz, par, si, 1, sc.slot0, sc.nslots, false, s));
+        }
+    }
+    if (reorth) {
+        lz_advance<<<1, 1, 0, s>>>(lz->dev, lz->m);
+        MBR_HIP(hipGetLastError());
+    }
+    return MBR_OK;
+}
+
+mbr_status step_any(mbr_lanczos *lz, int par, hipStream_t s) {
+    return lz->prec == MBR_F64 ? enqueue_step<double>(lz, par, s) : enqueue_step<float>(lz, par, s);
+}
+
+mbr_status capture(mbr_lanczos *lz, int par) {
+    if (!lz->cap_stream) MBR_HIP(hipStreamCreateWithFlags(&lz->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    MBR_HIP(hipStreamBeginCapture(lz->cap_stream, hipStreamCaptureModeThreadLocal));
+    mbr_status st = step_any(lz, par, lz->cap_stream);
+    hipError_t e = hipStreamEndCapture(lz->cap_stream, &g);
+    if (st != MBR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) MBR_FAIL(MBR_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&lz->graph[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) MBR_FAIL(MBR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    return MBR_OK;
+}
+
+template <class T>
+mbr_status lz_start_t(mbr_lanczos *lz, const double *v0, hipStream_t s) {
+    const HvSector *secs = lz->d_secs.as<HvSector>();
+    const HvTile *tiles = lz->d_tiles_slot.as<HvTile>();
+    const unsigned eg = (unsigned)std::min<uint64_t>((lz->total + kBlock - 1) / kBlock, 8192);
+    const bool reorth = lz->o.reorth != 0;
+    T *X = reorth ? lz->work.as<T>() : lz->bufA.as<T>();
+    lz_convert<T><<<eg, kBlock, 0, s>>>(v0, X, lz->total);
+    if (!reorth) lz_fill_zero<T><<<eg, kBlock, 0, s>>>(lz->bufB.as<T>(), lz->total);
+    lz_norm_parts<T><<<lz->grid, kBlock, 0, s>>>(tiles, lz->n_slots, secs, X, lz->dev.pn);
+    lz_start_scalars<<<lz->ns, kBlock, 0, s>>>(secs, lz->dev, reorth ? 1 : 0);
+    if (reorth)
+        lz_scale_into<T><<<lz->grid, kBlock, 0, s>>>(tiles, lz->n_slots, secs, X, lz->basis.as<T>(),
+                                                      lz->total, lz->dev, 0);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o, mbr_lanczos **out) {
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!h || !o) MBR_FAIL(MBR_EINVAL, "null Hamiltonian or options");
+    if (o->max_steps < 1 || o->max_steps > 4096) MBR_FAIL(MBR_EINVAL, "max_steps=%d outside 1..4096", o->max_steps);
+    if (o->breakdown_tol < 0) MBR_FAIL(MBR_EINVAL, "negative breakdown tolerance");
+    auto lz = std::make_unique<mbr_lanczos>();
+    lz->h = h;
+    lz->o = *o;
+    lz->ns = hubbard_n_sectors(h);
+    lz->m = o->max_steps;
+    lz->prec = hubbard_precision(h);
+    lz->tsz = lz->prec == MBR_F64 ? 8 : 4;
+    lz->total = hubbard_total(h);
+    lz->n_slots = hubbard_n_slots(h);
+    lz->secs = hubbard_sectors(h);
+    const auto &tiles = hubbard_tiles(h);
+    hipStream_t s = nullptr;
+    MBR_TRY(upload(lz->d_tiles_slot, tiles.data(), tiles.size() * sizeof(HvTile), s));
+    MBR_TRY(upload(lz->d_secs, lz->secs.data(), lz->secs.size() * sizeof(HvSector), s));
+    const size_t ns = lz->ns, m = lz->m, nsl = lz->n_slots;
+    if (o->reorth) {
+        const double bytes = (double)lz->total * lz->tsz * (m + 2);
+        if (bytes > 250e9) MBR_FAIL(MBR_ENOMEM, "basis of %.1f GB", bytes / 1e9);
+        MBR_TRY(lz->basis.alloc(lz->total * lz->tsz * (m + 1)));
+        MBR_TRY(lz->work.alloc(lz->total * lz->tsz));
+        MBR_TRY(lz->pc.alloc(nsl * (m + 1) * 8));
+        MBR_TRY(lz->cgs.alloc(ns * (m + 1) * 8));
+    } else {
+        MBR_TRY(lz->bufA.alloc(lz->total * lz->tsz));
+        MBR_TRY(lz->bufB.alloc(lz->total * lz->tsz));
+    }
+    MBR_TRY(lz->alpha.alloc(ns * m * 8));
+    MBR_TRY(lz->beta.alloc(ns * m * 8));
+    MBR_TRY(lz->c1.alloc(ns * 8));
+    MBR_TRY(lz->c2.alloc(ns * 8));
+    MBR_TRY(lz->c3.alloc(ns * 8));
+    MBR_TRY(lz->pd.alloc(nsl * 8));
+    MBR_TRY(lz->pn.alloc(nsl * 8));
+    MBR_TRY(lz->norm0.alloc(ns * 8));
+    MBR_TRY(lz->active.alloc(ns * 4));
+    MBR_TRY(lz->steps.alloc(ns * 4));
+    MBR_TRY(lz->jcount.alloc(8));
+    MBR_TRY(lz->e0.alloc(ns * 8));
+    MBR_HIP(hipMemset(lz->alpha.p, 0, ns * m * 8));
+    MBR_HIP(hipMemset(lz->beta.p, 0, ns * m * 8));
+    MBR_HIP(hipMemset(lz->active.p, 0, ns * 4));
+    MBR_HIP(hipMemset(lz->steps.p, 0, ns * 4));
+    MBR_HIP(hipMemset(lz->jcount.p, 0, 8));
+    LzDev &d = lz->dev;
+    d.alpha = lz->alpha.as<double>();
+    d.beta = lz->beta.as<double>();
+    d.c1 = lz->c1.as<double>();
+    d.c2 = lz->c2.as<double>();
+    d.c3 = lz->c3.as<double>();
+    d.pd = lz->pd.as<double>();
+    d.pn = lz->pn.as<double>();
+    d.pc = lz->pc.as<double>();
+    d.cgs = lz->cgs.as<double>();
+    d.norm0 = lz->norm0.as<double>();
+    d.active = lz->active.as<int32_t>();
+    d.steps = lz->steps.as<int32_t>();
+    d.j = lz->jcount.as<int32_t>();
+    lz->grid = (unsigned)std::min<uint64_t>(lz->n_slots, (uint64_t)device_cu_count() * 8);
+    *out = lz.release();
+    return MBR_OK;
+}
+
+mbr_status mbr_lanczos_start(mbr_lanczos *lz, const double *d_v0, void *stream) {
+    if (!lz || !d_v0) MBR_FAIL(MBR_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    lz->parity = 0;
+    lz->started = true;
+    if (lz->prec == MBR_F64) return lz_start_t<double>(lz, d_v0, s);
+    return lz_start_t<float>(lz, d_v0, s);
+}
+
+mbr_status mbr_lanczos_step(mbr_lanczos *lz, int32_t nsteps, void *stream) {
+    if (!lz) MBR_FAIL(MBR_EINVAL, "null handle");
+    if (!lz->started) MBR_FAIL(MBR_EINVAL, "mbr_lanczos_start has not been called");
+    if (nsteps < 0) MBR_FAIL(MBR_EINVAL, "nsteps=%d", nsteps);
+    hipStream_t s = as_stream(stream);
+    const bool reorth = lz->o.reorth != 0;
+    for (int i = 0; i < nsteps; ++i) {
+        const int par = reorth ? 0 : lz->parity;
+        if (lz->o.use_graph) {
+            if (!lz->graph[par]) MBR_TRY(capture(lz, par));
+            MBR_HIP(hipGraphLaunch(lz->graph[par], s));
+        } else {
+            MBR_TRY(step_any(lz, par, s));
+        }
+        if (!reorth) lz->parity ^= 1;
+    }
+    return MBR_OK;
+}
+
+mbr_status mbr_lanczos_result(mbr_lanczos *lz, double *e0, int32_t *steps_done, void *stream) {
+    if (!lz) MBR_FAIL(MBR_EINVAL, "null handle");
+    hipStream_t s = as_stream(stream);
+    tridiag_lowest_kernel<<<lz->ns, 64, 0, s>>>(lz->dev.alpha, lz->dev.beta, lz->dev.steps, lz->m,
+                                                lz->ns, lz->e0.as<double>());
+    MBR_HIP(hipGetLastError());
+    if (e0) MBR_HIP(hipMemcpyAsync(e0, lz->e0.p, lz->ns * 8, hipMemcpyDeviceToHost, s));
+    if (steps_done) MBR_HIP(hipMemcpyAsync(steps_done, lz->dev.steps, lz->ns * 4, hipMemcpyDeviceToHost, s));
+    MBR_HIP(hipStreamSynchronize(s));
+    return MBR_OK;
+}
+
+mbr_status mbr_lanczos_coeffs(mbr_lanczos *lz, double *alpha, double *beta, void *stream) {
+    if (!lz) MBR_FAIL(MBR_EINVAL, "null handle");
+    hipStream_t s = as_stream(stream);
+    const size_t n = (size_t)lz->ns * lz->m * 8;
+    if (alpha) MBR_HIP(hipMemcpyAsync(alpha, lz->dev.alpha, n, hipMemcpyDeviceToHost, s));
+    if (beta) MBR_HIP(hipMemcpyAsync(beta, lz->dev.beta, n, hipMemcpyDeviceToHost, s));
+    MBR_HIP(hipStreamSynchronize(s));
+    return MBR_OK;
+}
+
+mbr_status mbr_lanczos_destroy(mbr_lanczos *lz) {
+    delete lz;
+    return MBR_OK;
+}
+
+mbr_status mbr_tridiag_lowest(const double *d_alpha, const double *d_beta, const int32_t *d_len,
+                              int32_t ld, int32_t n_batch, double *d_e0, void *stream) {
+    if (n_batch < 0 || ld < 1) MBR_FAIL(MBR_EINVAL, "ld=%d n_batch=%d", ld, n_batch);
+    if (n_batch == 0) return MBR_OK;
+    if (!d_alpha || !d_beta || !d_len || !d_e0) MBR_FAIL(MBR_EINVAL, "null pointer");
+    tridiag_lowest_kernel<<<n_batch, 64, 0, as_stream(stream)>>>(d_alpha, d_beta, d_len, ld, n_batch,
+                                                                 d_e0);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+}  // extern "C"

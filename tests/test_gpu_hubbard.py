@@ -1,0 +1,235 @@
+"""GPU parity of the on-the-fly Hubbard H·x and of the Lanczos driver.
+
+H·x is compared element by element with the oracle's tuple-built Hamiltonian
+(Eq. Talpha2 with bisection ranks).  Floating-point bound per row: the two
+sides sum the same terms in different orders, so |y_gpu - y_oracle| is at most
+about n_terms * eps * sum_terms |v x|; the tests use 64 eps * abssum, with
+eps of the vector precision (the fp32 path rounds x to fp32 on both sides and
+accumulates in fp32 on the GPU).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hamiltonian as OH
+from oracle import lanczos as OL
+import synth
+from tests._util import say
+
+pytestmark = pytest.mark.gpu
+mbr = pytest.importorskip("paper_2203_04158_amd")
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+EPS64, EPS32 = 2.0 ** -52, 2.0 ** -23
+
+
+def _dev(a, prec):
+    dt = torch.float64 if prec == mbr.F64 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def _check_apply(L, bonds, sectors, U, eps, prec, seed, k=0, rows_per_sector=None):
+    h = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps, precision=prec, k=k)
+    x = 2 * synth.uniform01(seed, h.dim) - 1
+    if prec == mbr.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x, prec)
+    yd = torch.empty_like(xd)
+    mbr.hubbard_apply(h, xd, yd)
+    y = yd.cpu().numpy().astype(np.float64)
+    tl = OH.terms(L, bonds, U if U is not None else 0.0, eps)
+    eps_p = EPS64 if prec == mbr.F64 else EPS32
+    for si, (nu, nd) in enumerate(sectors):
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        st = OH.sector(L, nu, nd)
+        assert st.size == o1 - o0
+        if rows_per_sector is None:
+            want, ab = OH.apply(st, tl, x[o0:o1], with_abssum=True)
+            got = y[o0:o1]
+        else:
+            n = st.size
+            rows = np.unique(np.concatenate([
+                [0, n - 1], np.arange(min(n, 70)),
+                synth.uniform_indices(seed + si, rows_per_sector, n)]))
+            want, ab = OH.apply(st, tl, x[o0:o1], rows=rows, with_abssum=True)
+            got = y[o0:o1][rows]
+        bad = np.abs(got - want) > 64 * eps_p * ab + 1e-300
+        assert not bad.any(), (si, nu, nd, np.nonzero(bad)[0][:5], got[bad][:5], want[bad][:5])
+    return h
+
+
+@pytest.mark.parametrize("L,periodic,U", [(2, False, 4.0), (3, True, 4.0), (4, True, 2.5),
+                                          (6, True, 4.0), (8, True, 1.0)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_all_sectors(L, periodic, U, prec):
+    say("chain", L, periodic, U, prec)
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    _check_apply(L, OH.chain_bonds(L, 1.0, periodic), sectors, [U] * L, None, prec, seed=L)
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 7, 10])
+def test_general_bonds_sites_and_chunks(k):
+    # arbitrary bond list (long range, both orders), site-dependent U and eps
+    L = 10
+    r = synth.uniform01(40 + k, 64)
+    bonds = [(0, 5, 0.7), (3, 1, -0.4), (9, 2, 1.3), (4, 8, 0.2), (7, 6, -1.1), (2, 3, 0.9),
+             (9, 0, 0.5)]
+    U = list(3 * r[:L])
+    U[4] = 0.0
+    eps = list(2 * r[L:2 * L] - 1)
+    sectors = [(5, 5), (3, 6), (1, 0), (10, 10), (0, 4), (7, 2)]
+    _check_apply(L, bonds, sectors, U, eps, mbr.F64, seed=k, k=k)
+
+
+def test_narrow_tiles_many_sectors_fp32():
+    # small C(L, n_dn) exercises the flattened-row path
+    L = 12
+    eps_b, V = synth.anderson_parameters(7, L - 1)
+    eps = [-4.0] + list(eps_b)
+    U = [8.0] + [0.0] * (L - 1)
+    sectors = [(6, 0), (6, 1), (5, 2), (0, 12), (12, 11), (1, 3), (6, 6), (11, 12)]
+    _check_apply(L, OH.star_bonds(V), sectors, U, eps, mbr.F32, seed=3, rows_per_sector=3000)
+
+
+def test_chain_l14_full_size_sampled():
+    L = 14
+    _check_apply(L, OH.chain_bonds(L), [(7, 7)], [4.0] * L, None, mbr.F64, seed=2,
+                 rows_per_sector=4000)
+
+
+def test_anderson_all_169_sectors_sampled_fp32():
+    L = 12
+    eps_b, V = synth.anderson_parameters(5, 11)
+    eps = [-4.0] + list(eps_b)
+    U = [8.0] + [0.0] * 11
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    h = _check_apply(L, OH.star_bonds(V), sectors, U, eps, mbr.F32, seed=5, rows_per_sector=60)
+    assert h.dim == 1 << 24
+
+
+def test_apply_rejects_aliasing_and_bad_desc():
+    h = mbr.hubbard_create(4, OH.chain_bonds(4), [(2, 2)], U=[1.0] * 4)
+    x = torch.zeros(h.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_apply(h, x, x)
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_create(4, [(0, 4, 1.0)], [(2, 2)])
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_create(17, [], [(2, 2)])
+
+
+# --------------------------------------------------------------------------- tridiagonal
+def test_tridiag_lowest_against_lapack():
+    rng_a = 2 * synth.uniform01(9, 64 * 300) - 1
+    rng_b = synth.uniform01(10, 64 * 300)
+    lens = np.array([1, 2, 3, 17, 64, 150, 200, 300] * 8, dtype=np.int32)
+    ld = 300
+    a = rng_a.reshape(64, ld) * 5
+    b = rng_b.reshape(64, ld) * 2
+    b[:4] = 1.0
+    a[:4] = 0.0
+    e = mbr.tridiag_lowest(torch.from_numpy(a.ravel()).cuda(), torch.from_numpy(b.ravel()).cuda(),
+                           torch.from_numpy(lens).cuda(), ld).cpu().numpy()
+    for i in range(64):
+        n = int(lens[i])
+        want = OL.tridiag_lowest(a[i, :n], b[i, :n])
+        assert abs(e[i] - want) <= 1e-13 * max(1.0, abs(want)), (i, n, e[i], want)
+    for i in range(4):
+        n = int(lens[i])
+        assert abs(e[i] - 2 * math.cos(math.pi * n / (n + 1))) < 1e-13
+
+
+# --------------------------------------------------------------------------- Lanczos
+def _run_lanczos(h, steps, seed, **kw):
+    lz = mbr.lanczos_create(h, steps, **kw)
+    v0 = synth.start_vector(seed, h.dim)
+    mbr.lanczos_start(lz, torch.from_numpy(v0).cuda())
+    mbr.lanczos_step(lz, steps)
+    e0, nst = mbr.lanczos_result(lz)
+    a, b = mbr.lanczos_coeffs(lz)
+    return e0, nst, a, b
+
+
+def test_lanczos_small_chain_fp64_matches_oracle_recurrence():
+    L, nu, nd = 6, 3, 3
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(nu, nd)], U=[4.0] * L)
+    e0, nst, a, b = _run_lanczos(h, 60, seed=2)
+    st = OH.sector(L, nu, nd)
+    A = OH.sparse(st, OH.terms(L, OH.chain_bonds(L), 4.0))
+    exact = np.linalg.eigvalsh(A.toarray())[0]
+    assert abs(e0[0] - exact) <= 1e-9 * abs(exact)
+    oa, ob = OL.lanczos(lambda v: A @ v, synth.start_vector(2, st.size), 60)
+    # early coefficients agree to rounding (the recurrence is the same)
+    assert np.allclose(a[0, :8], oa[:8], rtol=1e-11, atol=1e-12)
+    assert np.allclose(b[0, :8], ob[:8], rtol=1e-11, atol=1e-12)
+    assert nst[0] == 60
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-6)])
+@pytest.mark.parametrize("batched", [True, False])
+def test_lanczos_all_sectors_reorth(prec, tol, batched):
+    L, U = 6, 4.0
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), sectors, U=[U] * L, precision=prec)
+    e0, nst, a, b = _run_lanczos(h, 150, seed=11, reorth=True, batched=batched)
+    tl = OH.terms(L, OH.chain_bonds(L), U)
+    for si, (nu, nd) in enumerate(sectors):
+        st = OH.sector(L, nu, nd)
+        exact = np.linalg.eigvalsh(OH.dense(st, tl))[0]
+        assert abs(e0[si] - exact) <= tol * max(1.0, abs(exact)), (nu, nd, e0[si], exact, nst[si])
+        assert nst[si] <= st.size
+
+
+def test_lanczos_graph_batched_and_repeat_are_bitwise_equal():
+    L = 8
+    sectors = [(4, 4), (3, 5), (1, 1), (8, 0)]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), sectors, U=[3.0] * L)
+    r1 = _run_lanczos(h, 40, seed=4, use_graph=True)
+    r2 = _run_lanczos(h, 40, seed=4, use_graph=False)
+    r3 = _run_lanczos(h, 40, seed=4, use_graph=True, batched=False)
+    r4 = _run_lanczos(h, 40, seed=4, use_graph=True)
+    for r in (r2, r3, r4):
+        assert np.array_equal(r1[2], r[2]) and np.array_equal(r1[3], r[3])
+        assert np.array_equal(r1[0], r[0])
+
+
+def test_lanczos_free_fermions_l10():
+    L = 10
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(5, 5), (3, 2)], U=[0.0] * L)
+    e0, nst, _, _ = _run_lanczos(h, 120, seed=3)
+    for si, (nu, nd) in enumerate([(5, 5), (3, 2)]):
+        want = OH.free_energy(L, OH.chain_bonds(L), nu, nd)
+        assert abs(e0[si] - want) <= 1e-9 * abs(want)
+
+
+def test_lanczos_chain_l14_200_steps_fp64():
+    g = json.load(open(os.path.join(GOLD, "hubbard_chain_L14.json")))
+    L = g["L"]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(g["n_up"], g["n_dn"])], U=[g["U"]] * L)
+    e0, nst, a, b = _run_lanczos(h, g["lanczos_steps"], seed=g["start_seed"])
+    say("L14 E0", e0[0], g["e0_exact"], g["e0_lanczos"])
+    assert nst[0] == g["lanczos_steps"]
+    assert abs(e0[0] - g["e0_exact"]) <= 1e-9 * abs(g["e0_exact"])
+    assert np.allclose(a[0, :10], g["alpha_first10"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(b[0, :10], g["beta_first10"], rtol=1e-10, atol=1e-12)
+
+
+def test_lanczos_anderson_169_sectors_mixed():
+    g = json.load(open(os.path.join(GOLD, "anderson_12.json")))
+    L = 12
+    eps = [g["eps_d"]] + g["eps_bath"]
+    U = [g["U"]] + [0.0] * 11
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    h = mbr.hubbard_create(L, OH.star_bonds(g["V"]), sectors, U=U, eps=eps, precision=mbr.F32)
+    e0, nst, _, _ = _run_lanczos(h, 150, seed=5, reorth=True)
+    worst = 0.0
+    for si, (nu, nd) in enumerate(sectors):
+        want = g["e0"][f"{nu},{nd}"]
+        rel = abs(e0[si] - want) / max(1.0, abs(want))
+        worst = max(worst, rel)
+        assert rel <= 1e-6, (nu, nd, e0[si], want, nst[si])
+    say("anderson worst rel err", worst, "E0", e0.min(), min(g["e0"].values()))

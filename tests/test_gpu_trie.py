@@ -1,0 +1,103 @@
+"""GPU parity of trie ranking (bit-exact) and its memory footprint."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import combinatorics as OC
+from oracle import trie as OT
+import synth
+from tests._util import dev_u32, dev_u64, host_rank, say
+
+pytestmark = pytest.mark.gpu
+mbr = pytest.importorskip("paper_2203_04158_amd")
+
+
+def _expected_entries(states, M, k):
+    """Entries of the GPU layout: the paper's packed count (chunks of k from the
+    least significant end, short chunk last) with the root widened to all 2^w0
+    slots, plus 2^w - 1 leading and 2^w trailing zeros on every other level."""
+    w = OT.chunk_widths(M, k, "last")
+    packed = OT.packed_size(states, w)
+    c0 = np.asarray(states, dtype=np.uint64) & np.uint64((1 << w[0]) - 1)
+    root_span = int(c0.max()) - int(c0.min()) + 1
+    return packed - root_span + (1 << w[0]) + sum(2 * (1 << wl) - 1 for wl in w[1:])
+
+
+def _check(M, cons, k, width=32, n_noise=20000, seed=1):
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons, width_bits=width)
+    assert s.size == st.size
+    r = mbr.build_trie(s, k)
+    info = r.info()
+    assert info.levels == -(-M // k)
+    if M - OT.chunk_widths(M, k, "last")[-1] <= 26:  # range of the oracle's size counter
+        assert info.bytes == 4 * _expected_entries(st, M, k)
+    dev = dev_u32 if width == 32 else dev_u64
+    got = host_rank(mbr.rank_batch(r, dev(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    lim = (1 << M) - 1 if M < 64 else (1 << 64) - 1
+    noise = synth.splitmix64(seed + M * 97 + k, n_noise) & np.uint64(lim)
+    over = (st[: min(1000, st.size)] | np.uint64(1 << M)) if M < width else np.zeros(0, np.uint64)
+    q = np.concatenate([noise, over, st[::max(1, st.size // 500)]])
+    got = host_rank(mbr.rank_batch(r, dev(q)))
+    assert np.array_equal(got, OC.bisect_rank(st, q))
+    return r
+
+
+def test_worked_example_sector():
+    _check(6, OC.constraints(6, 2), 2)
+
+
+@pytest.mark.parametrize("M,N,k", [(12, 6, 1), (12, 6, 2), (13, 5, 3), (16, 8, 4), (16, 8, 5),
+                                   (20, 10, 8), (24, 12, 8), (16, 3, 16), (17, 8, 16), (9, 0, 4),
+                                   (9, 9, 4)])
+def test_particle_number_sectors(M, N, k):
+    say("trie", M, N, k)
+    _check(M, OC.constraints(M, N), k)
+
+
+@pytest.mark.parametrize("k", [3, 4, 8])
+def test_irregular_sectors(k):
+    _check(20, OC.constraints(20, 10, [(0xFF, 6, 8)]), k)           # RAS-like
+    _check(18, [(0x3FFFF, 7, 9), (0x5555, 2, 5)], k)                 # mixed N
+    _check(24, OC.spin_constraints(12, 6, 5), k)                     # spin product
+
+
+def test_u64_sector():
+    _check(40, OC.constraints(40, 3, [(0xF, 1, 2)]), 8, width=64)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_ras_m32_full_size(k):
+    """M = 32, N = 16 with at least 6 of orbitals 0-7 occupied (66,110,671
+    states); 2^24 queries, 90% members drawn uniformly by index and 10%
+    popcount-16 patterns with at most 5 of orbitals 0-7 occupied."""
+    M = 32
+    cons = OC.constraints(M, 16, [(0xFF, 6, 8)])
+    st = OC.sector_enumerate(M, cons)
+    assert st.size == 66110671
+    s = mbr.sector_build(M, cons)
+    r = mbr.build_trie(s, k)
+    say("ras trie k", k, "bytes", r.info().bytes, "f", r.info().bytes / 4 / st.size)
+    nq = 1 << 24
+    nm = nq // 10
+    idx = synth.uniform_indices(3, nq - nm, st.size)
+    pool = synth.random_subset_patterns(33, 3 * nm, 32, 16)
+    low = np.array([bin(int(v) & 0xFF).count("1") for v in pool])
+    non = pool[low <= 5][:nm]
+    assert non.size == nm
+    q = np.concatenate([st[idx], non])
+    perm = synth.shuffle_positions(34, q.size)
+    q = q[perm]
+    want = np.concatenate([idx, np.full(nm, -1)])[perm]
+    got = host_rank(mbr.rank_batch(r, dev_u32(q)))
+    assert np.array_equal(got, want)
+
+
+def test_trie_rejects_bad_args():
+    s = mbr.sector_build(10, OC.constraints(10, 5))
+    with pytest.raises(mbr.MbrError):
+        mbr.build_trie(s, 0)
+    with pytest.raises(mbr.MbrError):
+        mbr.build_trie(s, 17)
