@@ -78,6 +78,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k", type=int, default=0, help="half-pattern chunk width (0 = automatic)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--G", type=int, default=-1,
+                    help="fixed launch shape: alpha_up blocks per tile (0 = alpha_dn-stationary kernel); "
+                         "implies --no-tune")
+    ap.add_argument("--block", type=int, default=512, help="tile-kernel block size with --G")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the H·x product (and one plain copy of x for counter calibration); "
+                         "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured on a single "
@@ -91,8 +99,24 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     h = mbr.hubbard_create(L, chain_bonds(L), [(NUP, NDN)], U=[U] * L, precision=mbr.F64, k=args.k)
+    if args.G >= 0:
+        cfg = mbr.hubbard_get_config(h)
+        mbr.hubbard_set_config(h, k=cfg["k"], G=args.G, block=args.block)
+    elif not args.no_tune:
+        mbr.hubbard_autotune(h, reps=5)
+    launch_cfg = mbr.hubbard_get_config(h)
     dim = h.dim
     v0 = torch.from_numpy(synth.start_vector(SEED, dim)).to(dev)
+
+    if args.kernel_only:
+        x = v0.clone()
+        y = torch.empty_like(x)
+        for _ in range(args.kernel_reps):
+            mbr.hubbard_apply(h, x, y)
+        y.copy_(x)  # plain copy of dim fp64 values: known traffic for calibration
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": True, "dim": dim, "launch": launch_cfg}), flush=True)
+        return
 
     # warm-up: graph capture, caches, clocks
     if args.warmup > 0:
@@ -151,7 +175,8 @@ def main():
         "config": {"workload": "hubbard_chain_L14_U4_sector7x7_lanczos_fp64",
                    "L": L, "t": 1.0, "U": U, "sector": [NUP, NDN], "dim": dim,
                    "lanczos_steps": steps, "ranker": "staggered halves",
-                   "start_vector_seed": SEED},
+                   "start_vector_seed": SEED,
+                   "launch": {k: launch_cfg[k] for k in ("k", "G", "block", "tiles")}},
         "granks_per_s": value * hops / 1e9,
         "hops_per_product": hops,
         "hv_kernel_ms": hv_ms,

@@ -249,6 +249,34 @@ mbr_status mbr_hubbard_apply(const mbr_hubbard *h, const void *d_x, void *d_y, v
 
 mbr_status mbr_hubbard_destroy(mbr_hubbard *h);
 
+/* Launch shape of the H·x kernel (extension: the paper has no GPU layout).
+ * k: half-pattern chunk width of the staggered rank; G: alpha_up blocks a
+ * workgroup holds (the down-hop ranks of a lane are reused G times); block:
+ * threads per workgroup (256 or 512).  tuned_ms is the autotuner's best time
+ * for one product (0 when not tuned). */
+typedef struct {
+    int32_t k;
+    int32_t G;
+    int32_t block;
+    int32_t tiles;
+    uint64_t lds_bytes;
+    double tuned_ms;
+} mbr_hubbard_cfg;
+
+mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg);
+
+/* Set the launch shape (k in 1..L, G in {1,2,4}, block in {256,512}); EUNSUPPORTED
+ * when the tiles would not fit the LDS.  Lanczos handles created before the
+ * change reject further steps (EINVAL): create them afterwards. */
+mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream);
+
+/* Time every supported (k, G, block) on this device with `reps` products of
+ * scratch vectors and keep the fastest.  If the environment variable
+ * MBR_AUTOTUNE_CACHE names a file, a matching entry (device, L, bonds,
+ * sectors, precision) is used without timing, and new results are appended;
+ * unreadable or malformed entries are ignored.  Synchronises `stream`. */
+mbr_status mbr_hubbard_autotune(mbr_hubbard *h, int32_t reps, void *stream);
+
 /* ======================================================================== */
 /* Lanczos ground-state search over every sector of a Hamiltonian            */
 /* ======================================================================== */

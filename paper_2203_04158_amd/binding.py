@@ -59,6 +59,11 @@ class HubbardDesc(C.Structure):
                 ("precision", C.c_int32), ("k", C.c_int32)]
 
 
+class HubbardCfg(C.Structure):
+    _fields_ = [("k", C.c_int32), ("G", C.c_int32), ("block", C.c_int32), ("tiles", C.c_int32),
+                ("lds_bytes", C.c_uint64), ("tuned_ms", C.c_double)]
+
+
 class LanczosOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("reorth", C.c_int32), ("batched", C.c_int32),
                 ("use_graph", C.c_int32), ("breakdown_tol", C.c_double)]
@@ -96,6 +101,9 @@ _SIGS = {
     "mbr_hubbard_dim": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p]),
     "mbr_hubbard_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_hubbard_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_hubbard_get_config": (C.c_int32, [C.c_void_p, C.POINTER(HubbardCfg)]),
+    "mbr_hubbard_set_config": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "mbr_hubbard_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mbr_lanczos_create": (C.c_int32, [C.c_void_p, C.POINTER(LanczosOpts), C.POINTER(C.c_void_p)]),
     "mbr_lanczos_start": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_lanczos_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
@@ -346,6 +354,23 @@ def hubbard_create(L: int, bonds, sectors, U=None, eps=None, precision: int = F6
 def hubbard_apply(h: Hubbard, x, y, stream=None):
     _check("mbr_hubbard_apply", lib().mbr_hubbard_apply(h.handle, _dptr(x), _dptr(y), _stream(stream)))
     return y
+
+
+def hubbard_get_config(h: Hubbard) -> dict:
+    c = HubbardCfg()
+    _check("mbr_hubbard_get_config", lib().mbr_hubbard_get_config(h.handle, C.byref(c)))
+    return {"k": c.k, "G": c.G, "block": c.block, "tiles": c.tiles, "lds_bytes": c.lds_bytes,
+            "tuned_ms": c.tuned_ms}
+
+
+def hubbard_set_config(h: Hubbard, k: int, G: int, block: int, stream=None):
+    _check("mbr_hubbard_set_config", lib().mbr_hubbard_set_config(h.handle, k, G, block,
+                                                                  _stream(stream)))
+
+
+def hubbard_autotune(h: Hubbard, reps: int = 5, stream=None) -> dict:
+    _check("mbr_hubbard_autotune", lib().mbr_hubbard_autotune(h.handle, reps, _stream(stream)))
+    return hubbard_get_config(h)
 
 
 # --------------------------------------------------------------------------- Lanczos

@@ -24,6 +24,10 @@ struct HvSector {
     uint32_t slot0, nslots; // partial-sum slots of the sector
     uint32_t wide;    // lanes over alpha_dn with blocks in registers (1) or flattened rows (0)
     uint32_t x_lds;   // x blocks staged in LDS (1) or gathered from memory (0)
+    uint32_t rows;    // handled by the alpha_dn-stationary kernel (1) or the tile kernel (0)
+    uint32_t gp;      // rows kernel: alpha_up blocks per tile (lanes over (block, alpha_dn))
+    uint32_t R;       // rows kernel: alpha_dn values per lane
+    uint32_t pad;
 };
 
 // Epilogue: y = H x (plain), or u = c1[s] (H x)_i - c2[s] p_i written to `out`
@@ -38,9 +42,10 @@ struct HvEpilogue {
     // stride (elements), j read from *basis_j on the device (p = x when j = 0).
     const int32_t *basis_j = nullptr;
     uint64_t basis_stride = 0;
-    // Tile subset (by slot order) instead of the whole product.
+    // Tile subset (by slot order) of one sector instead of the whole product.
     const HvTile *tiles = nullptr;
     uint32_t n_tiles = 0;
+    uint32_t sector = 0;
 };
 
 struct HubbardImpl;
@@ -52,6 +57,8 @@ mbr_status hubbard_launch(const mbr_hubbard *h, const void *x, void *out, const 
 // Tiles in slot order (sector-contiguous), for per-sector launches and the
 // elementwise Lanczos kernels.
 const std::vector<HvTile> &hubbard_tiles(const mbr_hubbard *h);
+// Incremented whenever the launch shape (and so the tile list) changes.
+uint32_t hubbard_generation(const mbr_hubbard *h);
 int hubbard_precision(const mbr_hubbard *h);
 int hubbard_n_sectors(const mbr_hubbard *h);
 uint64_t hubbard_total(const mbr_hubbard *h);

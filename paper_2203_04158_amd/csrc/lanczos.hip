@@ -359,6 +359,7 @@ struct mbr_lanczos {
     LzDev dev{};
     int parity = 0;  // plain path: 0 -> q_j in A, 1 -> q_j in B
     bool started = false;
+    uint32_t generation = 0;  // Hamiltonian launch shape the tiles were taken from
     unsigned grid = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;
@@ -394,6 +395,7 @@ mbr_status enqueue_plain(mbr_lanczos *lz, int par, uint32_t s0, uint32_t nsec, u
     if (!all) {
         ep.tiles = tiles;
         ep.n_tiles = nt;
+        ep.sector = s0;
     }
     MBR_TRY(hubbard_launch(lz->h, X, P, ep, s));
     const unsigned g = std::min<unsigned>(lz->grid, nt);
@@ -422,6 +424,7 @@ mbr_status enqueue_reorth(mbr_lanczos *lz, uint32_t s0, uint32_t nsec, uint32_t 
     if (!all) {
         ep.tiles = tiles;
         ep.n_tiles = nt;
+        ep.sector = s0;
     }
     MBR_TRY(hubbard_launch(lz->h, V, W, ep, s));
     const unsigned g = std::min<unsigned>(lz->grid, nt);
@@ -515,6 +518,7 @@ mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o, m
     lz->total = hubbard_total(h);
     lz->n_slots = hubbard_n_slots(h);
     lz->secs = hubbard_sectors(h);
+    lz->generation = hubbard_generation(h);
     const auto &tiles = hubbard_tiles(h);
     hipStream_t s = nullptr;
     MBR_TRY(upload(lz->d_tiles_slot, tiles.data(), tiles.size() * sizeof(HvTile), s));
@@ -580,6 +584,8 @@ mbr_status mbr_lanczos_step(mbr_lanczos *lz, int32_t nsteps, void *stream) {
     if (!lz) MBR_FAIL(MBR_EINVAL, "null handle");
     if (!lz->started) MBR_FAIL(MBR_EINVAL, "mbr_lanczos_start has not been called");
     if (nsteps < 0) MBR_FAIL(MBR_EINVAL, "nsteps=%d", nsteps);
+    if (lz->generation != hubbard_generation(lz->h))
+        MBR_FAIL(MBR_EINVAL, "the Hamiltonian's launch shape changed after this Lanczos handle was created");
     hipStream_t s = as_stream(stream);
     const bool reorth = lz->o.reorth != 0;
     for (int i = 0; i < nsteps; ++i) {

@@ -1,0 +1,630 @@
+// Learned index for ranking (an extension; the paper has none): a per-sector
+// network 32 bit features -> 64 -> 64 -> 1 (ReLU) predicts rank / N_s.  The
+// largest prediction error e over all members, measured with the query kernel
+// itself, bounds an exact bisection in states[p - e .. p + e], so answers are
+// exact: a member is always inside its window and a non-member is never found.
+// When e exceeds the caller's bound the fallback ranker answers instead.
+//
+// Parameters (6337 fp32 masters): W1[64][32], b1[64], W2[64][64], b2[64],
+// w3[64], b3.  Queries use their bf16 roundings with fp32 accumulation.
+//
+// Inference runs on the matrix cores, v_mfma_f32_16x16x16bf16 (wave64): a wave
+// evaluates 16 queries per product chain.  Layers are computed transposed,
+// D = W * H^T (features x queries), because the 16x16 fp32 output fragment of
+// one layer (lane l holds features 4*(l/16)+r of query l%16) is exactly the
+// lane layout of the next product's B operand (K = features, N = queries);
+// activations go from fp32 to bf16 in registers, with no shuffles between
+// layers.  Training runs in fp32 on the vector ALUs (forward with the bf16
+// weights, backward, fixed-order batch reductions, Adam).
+#include <cmath>
+#include <memory>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kIn = 32, kH = 64;
+constexpr int P_W1 = 0, P_B1 = 2048, P_W2 = 2112, P_B2 = 6208, P_W3 = 6272, P_B3 = 6336;
+constexpr int kParams = 6337;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t f2bf(float f) {
+    // round to nearest even (finite inputs)
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf2f(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Per-lane weight fragments of the three products (A operands), biases in the
+// output-fragment layout.
+struct MlpFrags {
+    bf16x4 w1[4][2];
+    bf16x4 w2[4][4];
+    bf16x4 w3[4];
+    float b1[4][4];
+    float b2[4][4];
+    float b3;
+};
+
+// wb: bf16 weights in parameter order.
+__device__ __forceinline__ void load_frags(MlpFrags &f, const uint16_t *__restrict__ wb) {
+    const int l = threadIdx.x & 63;
+    const int row = l & 15, kg = (l >> 4) * 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                f.w1[t][ks][j] = (short)wb[P_W1 + (16 * t + row) * kIn + 16 * ks + kg + j];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                f.w2[t][ks][j] = (short)wb[P_W2 + (16 * t + row) * kH + 16 * ks + kg + j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            f.b1[t][r] = bf2f(wb[P_B1 + 16 * t + kg + r]);
+            f.b2[t][r] = bf2f(wb[P_B2 + 16 * t + kg + r]);
+        }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            f.w3[ks][j] = row == 0 ? (short)wb[P_W3 + 16 * ks + kg + j] : (short)0;
+    f.b3 = bf2f(wb[P_B3]);
+}
+
+__device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc, const float *bias) {
+    bf16x4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float v = acc[r] + bias[r];
+        o[r] = (short)f2bf(v > 0.f ? v : 0.f);
+    }
+    return o;
+}
+
+// Network output for the 16 queries held by lanes 16*grp .. 16*grp+15 of the
+// wave (pattern in `q` of each lane).  The result is valid in lanes 0..15,
+// lane n holding the output of query 16*grp + n.  All 64 lanes must call.
+__device__ __forceinline__ float mlp16(const MlpFrags &f, uint32_t q, int grp) {
+    const int l = threadIdx.x & 63;
+    const uint32_t a = (uint32_t)__shfl((int)q, 16 * grp + (l & 15), 64);
+    const int kg = (l >> 4) * 4;
+    bf16x4 xb[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xb[ks][j] = ((a >> (16 * ks + kg + j)) & 1u) ? (short)0x3F80 : (short)0;
+    bf16x4 h1[4], h2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[t][ks], xb[ks], acc, 0, 0, 0);
+        h1[t] = relu_bf16(acc, f.b1[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w2[t][ks], h1[ks], acc, 0, 0, 0);
+        h2[t] = relu_bf16(acc, f.b2[t]);
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w3[ks], h2[ks], acc, 0, 0, 0);
+    return acc[0] + f.b3;
+}
+
+// Network outputs for the 64 queries of a wave, each lane receiving its own.
+__device__ __forceinline__ float mlp64(const MlpFrags &f, uint32_t q) {
+    const int l = threadIdx.x & 63;
+    const float y0 = mlp16(f, q, 0), y1 = mlp16(f, q, 1), y2 = mlp16(f, q, 2), y3 = mlp16(f, q, 3);
+    const float s0 = __shfl(y0, l & 15, 64), s1 = __shfl(y1, l & 15, 64);
+    const float s2 = __shfl(y2, l & 15, 64), s3 = __shfl(y3, l & 15, 64);
+    const int g = l >> 4;
+    return g == 0 ? s0 : g == 1 ? s1 : g == 2 ? s2 : s3;
+}
+
+__device__ __forceinline__ int64_t predict_rank(float y, uint64_t n) {
+    double p = rint((double)n * (double)y);
+    if (!(p >= 0.0)) p = 0.0;  // also NaN
+    if (p > (double)(n - 1)) p = (double)(n - 1);
+    return (int64_t)p;
+}
+
+// ---------------------------------------------------------------- inference
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const uint16_t *__restrict__ wb,
+                                                          const uint32_t *__restrict__ q, int B,
+                                                          float *__restrict__ out) {
+    MlpFrags f;
+    load_frags(f, wb);
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < B; base += waves * 64) {
+        const int i = base + (threadIdx.x & 63);
+        const uint32_t a = i < B ? q[i] : 0u;
+        const float y = mlp64(f, a);
+        if (i < B) out[i] = y;
+    }
+}
+
+// Largest |p(alpha_i) - i| over the sector (the query kernel's arithmetic).
+__global__ void __launch_bounds__(256) mlp_maxerr_kernel(const uint16_t *__restrict__ wb,
+                                                         const uint32_t *__restrict__ states,
+                                                         uint64_t n, unsigned long long *emax) {
+    MlpFrags f;
+    load_frags(f, wb);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long e = 0;
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + (threadIdx.x & 63);
+        const uint32_t a = i < n ? states[i] : 0u;
+        const float y = mlp64(f, a);
+        if (i < n) {
+            const int64_t p = predict_rank(y, n);
+            const unsigned long long d = (unsigned long long)(p > (int64_t)i ? p - (int64_t)i : (int64_t)i - p);
+            e = d > e ? d : e;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long v = __shfl_down(e, o, 64);
+        e = v > e ? v : e;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(emax, e);
+}
+
+__global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__restrict__ wb,
+                                                           const uint32_t *__restrict__ states,
+                                                           uint64_t n, uint64_t e, int M,
+                                                           const uint32_t *__restrict__ q, uint64_t nq,
+                                                           uint32_t *__restrict__ out) {
+    MlpFrags f;
+    load_frags(f, wb);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < nq;
+         base += waves * 64) {
+        const uint64_t j = base + (threadIdx.x & 63);
+        const uint32_t a = j < nq ? q[j] : 0u;
+        const float y = mlp64(f, a);
+        if (j >= nq) continue;
+        const bool in_width = M >= 32 || (a >> M) == 0;
+        const int64_t p = predict_rank(y, n);
+        uint64_t lo = p > (int64_t)e ? (uint64_t)(p - (int64_t)e) : 0;
+        uint64_t hi = (uint64_t)p + e;
+        if (hi > n - 1) hi = n - 1;
+        // lower bound of a in states[lo .. hi]
+        uint64_t L = lo, R = hi + 1;
+        while (L < R) {
+            const uint64_t mid = (L + R) >> 1;
+            if (states[mid] < a) L = mid + 1;
+            else R = mid;
+        }
+        const bool hit = in_width && L <= hi && states[L] == a;
+        out[j] = hit ? (uint32_t)L : MBR_NOT_FOUND;
+    }
+}
+
+// ---------------------------------------------------------------- training
+// SplitMix64, element k of the stream of `seed` (the generator the sample
+// draws are defined by).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Scratch of one batch, feature-major ([feature][sample]) so that the
+// per-sample threads write and the reduction reads contiguous rows.
+struct TrainScratch {
+    float *h1, *h2, *dz1, *dz2;  // [64][B]
+    float *dy;                   // [B]
+    uint32_t *x;                 // [B] patterns
+    float *loss_part;            // [B / 64]
+};
+
+// One thread per sample: forward with bf16-rounded weights in fp32, loss,
+// backward to dz2 and dz1.  Samples come from (q, tgt) when given, else are
+// drawn from the sector: idx = splitmix64(seed, step*B + s) mod n.
+__global__ void __launch_bounds__(64) mlp_fwd_bwd_kernel(const float *__restrict__ wr, int B,
+                                                         const uint32_t *__restrict__ q,
+                                                         const float *__restrict__ tgt,
+                                                         const uint32_t *__restrict__ states,
+                                                         uint64_t n, uint64_t seed, uint64_t step,
+                                                         TrainScratch S) {
+    __shared__ float w1[kH * kIn], w2[kH * kH], b1[kH], b2[kH], w3[kH];
+    __shared__ float sh1[kH][64], sdz2[kH][64];  // per-thread vectors, [feature][thread]
+    const int tid = threadIdx.x;
+    for (int i = threadIdx.x; i < kH * kIn; i += blockDim.x) w1[i] = wr[P_W1 + i];
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) w2[i] = wr[P_W2 + i];
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        b1[i] = wr[P_B1 + i];
+        b2[i] = wr[P_B2 + i];
+        w3[i] = wr[P_W3 + i];
+    }
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.f;
+    if (s < B) {
+        uint32_t a;
+        float t;
+        if (q) {
+            a = q[s];
+            t = tgt[s];
+        } else {
+            const uint64_t idx = splitmix64_at(seed, step * (uint64_t)B + (uint64_t)s) % n;
+            a = states[idx];
+            t = (float)((double)idx / (double)n);
+        }
+        S.x[s] = a;
+        for (int i = 0; i < kH; ++i) {
+            float z = b1[i];
+            uint32_t m = a;
+            while (m) {
+                const int k = __ffs(m) - 1;
+                m &= m - 1;
+                z += w1[i * kIn + k];
+            }
+            const float h = z > 0.f ? z : 0.f;
+            sh1[i][tid] = h;
+            S.h1[(size_t)i * B + s] = h;
+        }
+        float y = wr[P_B3];
+        for (int j = 0; j < kH; ++j) {
+            float z = b2[j];
+#pragma unroll 16
+            for (int i = 0; i < kH; ++i) z += w2[j * kH + i] * sh1[i][tid];
+            const float h = z > 0.f ? z : 0.f;
+            S.h2[(size_t)j * B + s] = h;
+            y += w3[j] * h;
+            sdz2[j][tid] = z > 0.f ? 1.f : 0.f;  // ReLU mask, scaled below
+        }
+        const float d = 2.f * (y - t) / (float)B;
+        sq = (y - t) * (y - t);
+        S.dy[s] = d;
+        for (int j = 0; j < kH; ++j) {
+            const float g = sdz2[j][tid] * d * w3[j];
+            sdz2[j][tid] = g;
+            S.dz2[(size_t)j * B + s] = g;
+        }
+        for (int i = 0; i < kH; ++i) {
+            float g = 0.f;
+#pragma unroll 16
+            for (int j = 0; j < kH; ++j) g += w2[j * kH + i] * sdz2[j][tid];
+            S.dz1[(size_t)i * B + s] = sh1[i][tid] > 0.f ? g : 0.f;
+        }
+    }
+    // per-wave partial of the squared error
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_down(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) S.loss_part[s >> 6] = sq;
+}
+
+constexpr int kChunk = 64;  // samples per gradient-partial workgroup
+
+// Gradient partials of one chunk of kChunk samples, all 6337 parameters.
+__global__ void __launch_bounds__(256) mlp_grad_part_kernel(int B, TrainScratch S, float *__restrict__ part) {
+    __shared__ float ta[kH][kChunk + 1];
+    __shared__ float tb[kH][kChunk + 1];
+    __shared__ uint32_t xs[kChunk];
+    __shared__ float dys[kChunk];
+    const int c0 = blockIdx.x * kChunk;
+    const int cn = min(kChunk, B - c0);
+    float *out = part + (size_t)blockIdx.x * kParams;
+    // phase A: dz2 (ta) and h1 (tb): gW2[j][i] = sum_s dz2[j][s] h1[i][s], gb2
+    for (int e = threadIdx.x; e < kH * kChunk; e += blockDim.x) {
+        const int f = e / kChunk, s = e % kChunk;
+        ta[f][s] = s < cn ? S.dz2[(size_t)f * B + c0 + s] : 0.f;
+        tb[f][s] = s < cn ? S.h1[(size_t)f * B + c0 + s] : 0.f;
+    }
+    for (int s = threadIdx.x; s < kChunk; s += blockDim.x) {
+        xs[s] = s < cn ? S.x[c0 + s] : 0u;
+        dys[s] = s < cn ? S.dy[c0 + s] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kH * kH; e += blockDim.x) {
+        const int j = e / kH, i = e % kH;
+        float g = 0.f;
+        for (int s = 0; s < kChunk; ++s) g += ta[j][s] * tb[i][s];
+        out[P_W2 + e] = g;
+    }
+    for (int j = threadIdx.x; j < kH; j += blockDim.x) {
+        float g = 0.f;
+        for (int s = 0; s < kChunk; ++s) g += ta[j][s];
+        out[P_B2 + j] = g;
+    }
+    __syncthreads();
+    // phase B: dz1 (ta) and h2 (tb): gW1[i][k] = sum_s dz1[i][s] x_k(s), gb1, gw3, gb3
+    for (int e = threadIdx.x; e < kH * kChunk; e += blockDim.x) {
+        const int f = e / kChunk, s = e % kChunk;
+        ta[f][s] = s < cn ? S.dz1[(size_t)f * B + c0 + s] : 0.f;
+        tb[f][s] = s < cn ? S.h2[(size_t)f * B + c0 + s] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kH * kIn; e += blockDim.x) {
+        const int i = e / kIn, k = e % kIn;
+        float g = 0.f;
+        for (int s = 0; s < kChunk; ++s) g += ((xs[s] >> k) & 1u) ? ta[i][s] : 0.f;
+        out[P_W1 + e] = g;
+    }
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        float g1 = 0.f, g3 = 0.f;
+        for (int s = 0; s < kChunk; ++s) {
+            g1 += ta[i][s];
+            g3 += dys[s] * tb[i][s];
+        }
+        out[P_B1 + i] = g1;
+        out[P_W3 + i] = g3;
+    }
+    if (threadIdx.x == 0) {
+        float g = 0.f;
+        for (int s = 0; s < kChunk; ++s) g += dys[s];
+        out[P_B3] = g;
+    }
+}
+
+// Sum the chunk partials in chunk order; optionally apply one Adam step to the
+// fp32 masters and refresh the rounded copies (fp32 value and bf16 bits).
+__global__ void mlp_reduce_adam_kernel(const float *__restrict__ part, int nchunk, float *grad,
+                                       float *w, float *m, float *v, float *wr, uint16_t *wb,
+                                       float lr, float b1c, float b2c, int adam) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    float g = 0.f;
+    for (int c = 0; c < nchunk; ++c) g += part[(size_t)c * kParams + p];
+    if (grad) grad[p] = g;
+    if (!adam) return;
+    const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+    const float mm = beta1 * m[p] + (1.f - beta1) * g;
+    const float vv = beta2 * v[p] + (1.f - beta2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / b1c, vh = vv / b2c;
+    const float nw = w[p] - lr * mh / (sqrtf(vh) + eps);
+    w[p] = nw;
+    const uint16_t b = f2bf(nw);
+    wb[p] = b;
+    wr[p] = bf2f(b);
+}
+
+__global__ void mlp_round_kernel(const float *__restrict__ w, float *wr, uint16_t *wb) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    const uint16_t b = f2bf(w[p]);
+    wb[p] = b;
+    wr[p] = bf2f(b);
+}
+
+__global__ void mlp_loss_kernel(const float *__restrict__ lp, int nparts, int B, float *loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float s = 0.f;
+    for (int i = 0; i < nparts; ++i) s += lp[i];
+    *loss = s / (float)B;
+}
+
+// Batch scratch of B samples.
+struct TrainBufs {
+    mbr::DevBuf scratch, part;
+    TrainScratch S{};
+    int B = 0;
+    mbr_status alloc(int b) {
+        B = b;
+        const size_t n = (size_t)b;
+        MBR_TRY(scratch.alloc(n * 4 * (4 * kH + 2) + (n / 64 + 1) * 4));
+        float *f = scratch.as<float>();
+        S.h1 = f;
+        S.h2 = f + n * kH;
+        S.dz1 = f + 2 * n * kH;
+        S.dz2 = f + 3 * n * kH;
+        S.dy = f + 4 * n * kH;
+        S.x = reinterpret_cast<uint32_t *>(f + 4 * n * kH + n);
+        S.loss_part = f + 4 * n * kH + 2 * n;
+        MBR_TRY(part.alloc((size_t)((b + kChunk - 1) / kChunk) * kParams * 4));
+        return MBR_OK;
+    }
+};
+
+// Forward/backward and chunk partials of one batch.
+mbr_status batch_grad(TrainBufs &T, const float *wr, const uint32_t *q, const float *tgt,
+                      const uint32_t *states, uint64_t n, uint64_t seed, uint64_t step, hipStream_t s) {
+    const int B = T.B;
+    mlp_fwd_bwd_kernel<<<(B + 63) / 64, 64, 0, s>>>(wr, B, q, tgt, states, n, seed, step, T.S);
+    mlp_grad_part_kernel<<<(B + kChunk - 1) / kChunk, 256, 0, s>>>(B, T.S, T.part.as<float>());
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+}  // namespace
+
+struct LearnedModel {
+    uint64_t n = 0;
+    int32_t M = 0;
+    mbr::DevBuf w, m, v, wr, wb;  // masters, Adam moments, rounded fp32, bf16
+    uint64_t e = 0;
+    int32_t uses_window = 0;
+    double last_loss = 0;
+};
+
+void learned_free(LearnedModel *m) { delete m; }
+uint64_t learned_bytes(const LearnedModel *m) { return m ? (uint64_t)kParams * 2 : 0; }
+
+mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                               hipStream_t s) {
+    const LearnedModel &lm = *r->learned;
+    if (!lm.uses_window) {
+        if (!r->fallback) MBR_FAIL(MBR_EINVAL, "learned ranker without window or fallback");
+        return mbr_rank_batch(r->fallback, q, n, out, s);
+    }
+    const unsigned grid = mbr::grid_for(n, 256, mbr::device_cu_count() * 8);
+    learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(),
+                                             lm.n, lm.e, lm.M, static_cast<const uint32_t *>(q), n, out);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+namespace {
+
+// He-uniform initialisation from SplitMix64 (host), biases zero.
+std::vector<float> init_params(uint64_t seed) {
+    std::vector<float> p(kParams, 0.f);
+    uint64_t k = 0;
+    auto u01 = [&]() {
+        uint64_t z = seed + (++k) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    const double a1 = std::sqrt(6.0 / kIn), a2 = std::sqrt(6.0 / kH), a3 = std::sqrt(3.0 / kH);
+    for (int i = 0; i < kH * kIn; ++i) p[P_W1 + i] = (float)((2 * u01() - 1) * a1);
+    for (int i = 0; i < kH * kH; ++i) p[P_W2 + i] = (float)((2 * u01() - 1) * a2);
+    for (int i = 0; i < kH; ++i) p[P_W3 + i] = (float)((2 * u01() - 1) * a3);
+    p[P_B3] = 0.5f;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
+                             const mbr_ranker *fallback, mbr_ranker **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!sec || !o) MBR_FAIL(MBR_EINVAL, "null sector or options");
+    if (sec->width_bits != 32) MBR_FAIL(MBR_EUNSUPPORTED, "learned ranking needs 32-bit patterns");
+    if (sec->n < 2) MBR_FAIL(MBR_EINVAL, "sector of %llu states", (unsigned long long)sec->n);
+    if (o->epochs < 0 || o->batch < 256 || o->batch % 256 != 0 || o->batch > (1 << 20))
+        MBR_FAIL(MBR_EINVAL, "epochs=%d batch=%d (batch: multiple of 256 up to 2^20)", o->epochs, o->batch);
+    if (!(o->lr > 0.f)) MBR_FAIL(MBR_EINVAL, "lr must be positive");
+    if (fallback && fallback->n_states != sec->n) MBR_FAIL(MBR_EINVAL, "fallback ranks a different sector");
+    hipStream_t s = as_stream(stream);
+    auto lm = std::make_unique<LearnedModel>();
+    lm->n = sec->n;
+    lm->M = sec->M;
+    std::vector<float> p0 = init_params(o->seed);
+    MBR_TRY(upload(lm->w, p0.data(), kParams * 4, s));
+    MBR_TRY(lm->m.alloc(kParams * 4));
+    MBR_TRY(lm->v.alloc(kParams * 4));
+    MBR_TRY(lm->wr.alloc(kParams * 4));
+    MBR_TRY(lm->wb.alloc(kParams * 2));
+    MBR_HIP(hipMemsetAsync(lm->m.p, 0, kParams * 4, s));
+    MBR_HIP(hipMemsetAsync(lm->v.p, 0, kParams * 4, s));
+    mlp_round_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(lm->w.as<float>(), lm->wr.as<float>(), lm->wb.as<uint16_t>());
+    TrainBufs T;
+    MBR_TRY(T.alloc(o->batch));
+    const uint64_t per_epoch = o->samples_per_epoch ? o->samples_per_epoch : sec->n;
+    const uint64_t steps_per_epoch = (per_epoch + o->batch - 1) / o->batch;
+    const uint64_t total = steps_per_epoch * (uint64_t)o->epochs;
+    const int nchunk = (o->batch + kChunk - 1) / kChunk;
+    double b1p = 1.0, b2p = 1.0;
+    for (uint64_t st = 0; st < total; ++st) {
+        MBR_TRY(batch_grad(T, lm->wr.as<float>(), nullptr, nullptr, sec->states.as<uint32_t>(), sec->n,
+                           o->seed, st, s));
+        b1p *= 0.9;
+        b2p *= 0.999;
+        // cosine decay of the step size over the run
+        const double lr = o->lr * 0.5 * (1.0 + std::cos(3.14159265358979323846 * (double)st / (double)total));
+        mlp_reduce_adam_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(
+            T.part.as<float>(), nchunk, nullptr, lm->w.as<float>(), lm->m.as<float>(), lm->v.as<float>(),
+            lm->wr.as<float>(), lm->wb.as<uint16_t>(), (float)lr, (float)(1.0 - b1p), (float)(1.0 - b2p), 1);
+        MBR_HIP(hipGetLastError());
+    }
+    // maximum error with the query kernel's own arithmetic
+    DevBuf d_e;
+    MBR_TRY(d_e.alloc(8));
+    MBR_HIP(hipMemsetAsync(d_e.p, 0, 8, s));
+    const unsigned grid = grid_for(sec->n, 256, device_cu_count() * 8);
+    mlp_maxerr_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
+                                           d_e.as<unsigned long long>());
+    MBR_HIP(hipGetLastError());
+    unsigned long long e = 0;
+    MBR_HIP(hipMemcpyAsync(&e, d_e.p, 8, hipMemcpyDeviceToHost, s));
+    MBR_HIP(hipStreamSynchronize(s));
+    lm->e = e;
+    lm->uses_window = (e <= o->max_window) ? 1 : 0;
+    if (!lm->uses_window && !fallback)
+        MBR_FAIL(MBR_ERANGE, "max error %llu exceeds max_window and no fallback was given", e);
+    auto *r = new (std::nothrow) mbr_ranker;
+    if (!r) MBR_FAIL(MBR_ENOMEM, "host allocation");
+    r->kind = MBR_RANKER_LEARNED;
+    r->M = sec->M;
+    r->k = 0;
+    r->width_bits = 32;
+    r->n_states = sec->n;
+    r->sector = sec;
+    r->fallback = fallback;
+    (void)hipGetDevice(&r->device);
+    r->learned = lm.release();
+    *out = r;
+    return MBR_OK;
+}
+
+mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses_window) {
+    if (!r || r->kind != MBR_RANKER_LEARNED) MBR_FAIL(MBR_EINVAL, "not a learned ranker");
+    if (e) *e = r->learned->e;
+    if (uses_window) *uses_window = r->learned->uses_window;
+    return MBR_OK;
+}
+
+mbr_status mbr_learned_params(const mbr_ranker *r, float *host_out, void *stream) {
+    if (!r || r->kind != MBR_RANKER_LEARNED || !host_out) MBR_FAIL(MBR_EINVAL, "bad argument");
+    hipStream_t s = mbr::as_stream(stream);
+    MBR_HIP(hipMemcpyAsync(host_out, r->learned->wr.p, kParams * 4, hipMemcpyDeviceToHost, s));
+    MBR_HIP(hipStreamSynchronize(s));
+    return MBR_OK;
+}
+
+mbr_status mbr_mlp_forward(const float *d_params, const uint32_t *d_q, int32_t B, float *d_pred,
+                           void *stream) {
+    using namespace mbr;
+    if (!d_params || !d_q || !d_pred) MBR_FAIL(MBR_EINVAL, "null pointer");
+    if (B <= 0 || B % 64 != 0) MBR_FAIL(MBR_EINVAL, "B=%d must be a positive multiple of 64", B);
+    hipStream_t s = as_stream(stream);
+    DevBuf wr, wb;
+    MBR_TRY(wr.alloc(kParams * 4));
+    MBR_TRY(wb.alloc(kParams * 2));
+    mlp_round_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(d_params, wr.as<float>(), wb.as<uint16_t>());
+    mlp_forward_kernel<<<grid_for((uint64_t)B, 256, 4096), 256, 0, s>>>(wb.as<uint16_t>(), d_q, B, d_pred);
+    MBR_HIP(hipGetLastError());
+    MBR_HIP(hipStreamSynchronize(s));  // scratch weights are released on return
+    return MBR_OK;
+}
+
+mbr_status mbr_mlp_gradients(const float *d_params, const uint32_t *d_q, const float *d_tgt, int32_t B,
+                             float *d_grad, float *d_loss, void *stream) {
+    using namespace mbr;
+    if (!d_params || !d_q || !d_tgt || !d_grad) MBR_FAIL(MBR_EINVAL, "null pointer");
+    if (B <= 0 || B % 64 != 0) MBR_FAIL(MBR_EINVAL, "B=%d must be a positive multiple of 64", B);
+    hipStream_t s = as_stream(stream);
+    DevBuf wr, wb;
+    MBR_TRY(wr.alloc(kParams * 4));
+    MBR_TRY(wb.alloc(kParams * 2));
+    mlp_round_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(d_params, wr.as<float>(), wb.as<uint16_t>());
+    TrainBufs T;
+    MBR_TRY(T.alloc(B));
+    MBR_TRY(batch_grad(T, wr.as<float>(), d_q, d_tgt, nullptr, 0, 0, 0, s));
+    mlp_reduce_adam_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(T.part.as<float>(), (B + kChunk - 1) / kChunk,
+                                                                 d_grad, nullptr, nullptr, nullptr, nullptr,
+                                                                 nullptr, 0.f, 1.f, 1.f, 0);
+    if (d_loss) mlp_loss_kernel<<<1, 1, 0, s>>>(T.S.loss_part, B / 64, B, d_loss);
+    MBR_HIP(hipGetLastError());
+    MBR_HIP(hipStreamSynchronize(s));
+    return MBR_OK;
+}
+
+}  // extern "C"

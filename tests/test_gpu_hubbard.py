@@ -233,3 +233,56 @@ def test_lanczos_anderson_169_sectors_mixed():
         worst = max(worst, rel)
         assert rel <= 1e-6, (nu, nd, e0[si], want, nst[si])
     say("anderson worst rel err", worst, "E0", e0.min(), min(g["e0"].values()))
+
+
+# --------------------------------------------------------------------------- launch shapes
+def test_every_launch_shape_gives_identical_products():
+    """Each row sums its terms in the same order whatever (k, G, block), so the
+    products are bitwise equal; the autotuner's choice is one of them."""
+    L = 14
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7), (6, 7)], U=[4.0] * L)
+    x = torch.from_numpy(2 * synth.uniform01(21, h.dim) - 1).cuda()
+    ref = None
+    for k in (7, 14, 5):
+        for G in (1, 2, 4):
+            for block in (256, 512):
+                mbr.hubbard_set_config(h, k, G, block)
+                y = torch.empty_like(x)
+                mbr.hubbard_apply(h, x, y)
+                if ref is None:
+                    ref = y.clone()
+                else:
+                    assert torch.equal(y, ref), (k, G, block)
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_set_config(h, 7, 3, 512)
+    cfg = mbr.hubbard_autotune(h, reps=2)
+    say("autotuned", cfg)
+    assert cfg["tuned_ms"] > 0 and cfg["G"] in (1, 2, 4)
+    y = torch.empty_like(x)
+    mbr.hubbard_apply(h, x, y)
+    assert torch.equal(y, ref)
+
+
+def test_autotune_cache_roundtrip_and_corrupt_entries(tmp_path, monkeypatch):
+    L = 8
+    cache = tmp_path / "tune.txt"
+    cache.write_text("garbage line\nanother 1 2\n")
+    monkeypatch.setenv("MBR_AUTOTUNE_CACHE", str(cache))
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(4, 4)], U=[2.0] * L)
+    c1 = mbr.hubbard_autotune(h, reps=1)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 3  # corrupt lines ignored, result appended
+    h2 = mbr.hubbard_create(L, OH.chain_bonds(L), [(4, 4)], U=[2.0] * L)
+    c2 = mbr.hubbard_autotune(h2, reps=1)
+    assert (c2["k"], c2["G"], c2["block"]) == (c1["k"], c1["G"], c1["block"])
+    assert len(cache.read_text().splitlines()) == 3  # served from the cache
+
+
+def test_lanczos_rejects_stale_launch_shape():
+    L = 6
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(3, 3)], U=[4.0] * L)
+    lz = mbr.lanczos_create(h, 10)
+    mbr.lanczos_start(lz, torch.from_numpy(synth.start_vector(1, h.dim)).cuda())
+    mbr.hubbard_set_config(h, 3, 1, 256)
+    with pytest.raises(mbr.MbrError):
+        mbr.lanczos_step(lz, 1)

@@ -1,0 +1,150 @@
+"""GPU parity of the learned index: network forward and gradients against the
+fp64 oracle, and exactness of learned ranking.
+
+Forward bound: the matrix-core path rounds each hidden activation to bf16
+(relative error <= 2^-9) and accumulates in fp32, so with the oracle's fp64
+intermediates h1, h2 (same bf16-rounded weights)
+  |y_gpu - y| <= 2^-8 * sum_j |w3_j| (sum_k |W2_jk| h1_k + h2_j) + 2^-16 * scale.
+Gradient bound: training keeps activations in fp32 (bf16 weights only), so the
+gradients agree with the fp64 oracle to fp32 accumulation error over the
+batch; the test uses 1e-4 of each tensor's largest entry.
+"""
+import numpy as np
+import pytest
+
+from oracle import combinatorics as OC
+from oracle import mlp as OM
+import synth
+from tests._util import dev_u32, host_rank, say
+
+pytestmark = pytest.mark.gpu
+mbr = pytest.importorskip("paper_2203_04158_amd")
+torch = pytest.importorskip("torch")
+
+
+def _bf16(a):
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _split(flat):
+    f = np.asarray(flat, dtype=np.float64)
+    return [f[0:2048].reshape(64, 32), f[2048:2112], f[2112:6208].reshape(64, 64),
+            f[6208:6272], f[6272:6336], float(f[6336])]
+
+
+def _random_params(seed, scale=1.0):
+    u = 2 * synth.uniform01(seed, 6337) - 1
+    u[:2048] *= 0.4 * scale
+    u[2048:2112] *= 0.1
+    u[2112:6208] *= 0.25 * scale
+    u[6208:6272] *= 0.1
+    u[6272:6336] *= 0.3
+    return u.astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_forward_matches_oracle(seed):
+    B = 2048
+    p32 = _random_params(seed)
+    q = (synth.splitmix64(seed + 100, B) & np.uint64(0xFFFFFFFF))
+    q[:4] = [0, 0xFFFFFFFF, 1, 1 << 31]
+    y = mbr.mlp_forward(torch.from_numpy(p32).cuda(), dev_u32(q)).cpu().numpy().astype(np.float64)
+    P = _split(_bf16(p32))
+    X = OM.features(q)
+    want, (X_, z1, h1, z2, h2) = OM.forward(P, X)
+    W1, b1, W2, b2, w3, b3 = P
+    bound = 2.0 ** -8 * (np.abs(w3) * (h1 @ np.abs(W2).T + h2)).sum(axis=1)
+    bound += 2.0 ** -16 * (1 + np.abs(want))
+    err = np.abs(y - want)
+    assert (err <= bound).all(), (err.max(), bound[err.argmax()])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_gradients_match_oracle(seed):
+    B = 512
+    p32 = _random_params(seed)
+    q = synth.splitmix64(seed + 7, B) & np.uint64(0xFFFFFF)
+    tgt = synth.uniform01(seed + 9, B).astype(np.float32)
+    g, loss = mbr.mlp_gradients(torch.from_numpy(p32).cuda(), dev_u32(q), torch.from_numpy(tgt).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    P = _split(_bf16(p32))
+    X = OM.features(q)
+    G = OM.gradients(P, X, tgt.astype(np.float64))
+    want_loss = OM.loss(P, X, tgt.astype(np.float64))
+    assert abs(float(loss.cpu()[0]) - want_loss) <= 1e-5 * max(1.0, want_loss)
+    got = _split(g)
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "w3", "b3"], got, G):
+        a = np.atleast_1d(a)
+        b = np.atleast_1d(b)
+        tol = 1e-4 * max(1e-12, np.abs(b).max())
+        assert np.abs(a - b).max() <= tol, (name, np.abs(a - b).max(), tol)
+
+
+def _learned(M, cons, epochs, batch=4096, lr=3e-3, max_window=1 << 20, k=8, seed=1):
+    s = mbr.sector_build(M, cons)
+    trie = mbr.build_trie(s, k)
+    lr_ = mbr.learned_train(s, trie, epochs=epochs, batch=batch, lr=lr, seed=seed,
+                            max_window=max_window)
+    return s, trie, lr_
+
+
+def test_learned_ranks_exact_and_error_recorded():
+    M, cons = 20, OC.constraints(20, 10)
+    st = OC.sector_enumerate(M, cons)
+    s, trie, lr_ = _learned(M, cons, epochs=30)
+    e, win = mbr.learned_max_error(lr_)
+    assert win
+    got = host_rank(mbr.rank_batch(lr_, dev_u32(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    noise = synth.splitmix64(77, 50000) & np.uint64((1 << 21) - 1)
+    got = host_rank(mbr.rank_batch(lr_, dev_u32(noise)))
+    assert np.array_equal(got, OC.bisect_rank(st, noise))
+    # the recorded e is the true maximum error of the query-time network
+    params = torch.from_numpy(mbr.learned_params(lr_)).cuda()
+    y = mbr.mlp_forward(params, dev_u32(np.concatenate([st, np.zeros((-st.size) % 64, np.uint64)])))
+    y = y.cpu().numpy().astype(np.float64)[: st.size]
+    p = np.clip(np.rint(st.size * y), 0, st.size - 1)
+    assert int(np.abs(p - np.arange(st.size)).max()) == e
+    say("learned M=20 N=10 e", e, "of", st.size)
+
+
+def test_training_gain_over_untrained_network():
+    M, cons = 20, OC.constraints(20, 10)
+    _, _, untrained = _learned(M, cons, epochs=0)
+    _, _, trained = _learned(M, cons, epochs=30)
+    e0, _ = mbr.learned_max_error(untrained)
+    e1, _ = mbr.learned_max_error(trained)
+    say("untrained e", e0, "trained e", e1)
+    assert e1 * 10 < e0
+
+
+def test_single_particle_sector_learns_exactly():
+    # N = 1: rank(2^c) = c is linear in the features; training reaches e = 0
+    M = 32
+    cons = OC.constraints(M, 1)
+    st = OC.sector_enumerate(M, cons)
+    s, trie, lr_ = _learned(M, cons, epochs=3000, batch=256, lr=1e-2)
+    e, win = mbr.learned_max_error(lr_)
+    say("N=1 e", e)
+    assert e == 0
+    assert np.array_equal(host_rank(mbr.rank_batch(lr_, dev_u32(st))), np.arange(M))
+
+
+def test_fallback_when_window_too_wide():
+    M, cons = 16, OC.constraints(16, 8, [(0xF, 3, 4)])
+    st = OC.sector_enumerate(M, cons)
+    s, trie, lr_ = _learned(M, cons, epochs=0, max_window=0)
+    e, win = mbr.learned_max_error(lr_)
+    assert not win and e > 0
+    q = np.concatenate([st, synth.splitmix64(3, 5000) & np.uint64(0xFFFF)])
+    assert np.array_equal(host_rank(mbr.rank_batch(lr_, dev_u32(q))), OC.bisect_rank(st, q))
+
+
+def test_training_is_repeatable():
+    M, cons = 14, OC.constraints(14, 7)
+    _, _, a = _learned(M, cons, epochs=5, seed=9)
+    _, _, b = _learned(M, cons, epochs=5, seed=9)
+    assert np.array_equal(mbr.learned_params(a), mbr.learned_params(b))
+    assert mbr.learned_max_error(a) == mbr.learned_max_error(b)
