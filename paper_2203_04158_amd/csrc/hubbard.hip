@@ -52,11 +52,13 @@ struct mbr_hubbard {
     std::vector<HvTile> tiles_binned;   // tile-kernel tiles, XCD ranges, natural order inside
     uint32_t xoff[kXcd + 1] = {0};
     std::vector<HvTile> rows_tiles;     // alpha_dn-stationary kernel tiles, natural order
-    DevBuf d_rows_tiles;
+    DevBuf d_rdesc, d_rdesc_slot;       // their descriptors, and descriptors in slot order
     uint32_t rows_xoff[kXcd + 1] = {0};
-    uint32_t rows_xcap = 0;
+    uint32_t rows_xcap = 0, rows_gmax = 1;
     int rows_R = 1, rows_grid = 0;
     bool t_uniform = true;              // all bonds share one amplitude
+    DevBuf d_lists;                     // rows kernel: down-hop lists per n_dn
+    std::vector<uint32_t> lists_ndn;    // n_dn of each list set, in storage order
     uint32_t n_slots = 0;
     StagTable tab;
     DevBuf d_hs_states, d_hs_energy, d_tiles, d_secs;
@@ -83,6 +85,15 @@ constexpr int kUpPre = 8;          // up-hop gathers issued ahead of the down-ho
 constexpr uint32_t kWideMin = 128; // C_dn from which lanes run over alpha_dn
 constexpr size_t kLdsMax = 160 * 1024;
 
+// Work descriptor of one tile of the alpha_dn-stationary kernel (host-built,
+// 32 bytes): first row of the tile and of its sector; C_dn | gp << 12 |
+// nblk << 20; half-state index of the first alpha_up | that of the alpha_dn
+// list << 16; down-hop list row | sector << 16; partial-sum slot.
+struct RowsTileDesc {
+    uint64_t base, soff;
+    uint32_t w0, w1, w2, slot;
+};
+
 struct HvArgs {
     const void *x;
     void *out;
@@ -108,6 +119,10 @@ struct HvArgs {
     uint32_t xcap;     // LDS elements for staged x rows
     uint32_t upcap;    // LDS up-hop list entries (max nblk * nb over tiles)
     uint32_t maxblk;   // LDS per-block entries (max nblk over tiles)
+    uint32_t rgmax;    // alpha_dn-stationary kernel: max alpha_up blocks per tile
+    int32_t t_uniform; // every bond has the amplitude bamp[0]
+    const void *lists;     // alpha_dn-stationary kernel: down-hop lists (hv_lists_kernel)
+    const RowsTileDesc *rdesc;  // and its tiles (n_tiles of them)
     HvEpilogue ep;
 };
 
@@ -143,6 +158,19 @@ __device__ __forceinline__ T u_energy(uint32_t both, const HvArgs &a) {
         e += (T)a.U[i];
     }
     return e;
+}
+
+template <class T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+// Fused Lanczos epilogue of one row: c1 (H x)_i - c2 p_i.
+template <class T>
+__device__ __forceinline__ T lz_out(T hx, T c1, T c2, T pv, bool has_p) {
+    const T u = c1 * hx;
+    return has_p ? fma_t(-c2, pv, u) : u;
 }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -214,11 +242,13 @@ __device__ __forceinline__ double wide_rows(const HvArgs &a, const uint16_t *rt,
             const bool hop = ((ad >> bi) ^ (ad >> bj)) & 1;
             uint32_t rr = rank_half<NCH>(ad ^ a.bmask[b], rt, a);
             rr = hop ? rr : rd;
-            T c = (__popc(ad & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
+            // uniform amplitude: sum the signed x and scale once, as the rows kernel does
+            const T mag = a.t_uniform ? (T)1 : (T)a.bamp[b];
+            T c = (__popc(ad & a.bbetw[b]) & 1) ? mag : -mag;
             c = hop ? c : (T)0;
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                if (g < nblk) acc[g] += c * xsrc[g * cdn + rr];
+                if (g < nblk) acc[g] = fma_t(c, xsrc[g * cdn + rr], acc[g]);
         }
         // 3. diagonal, up-hops, epilogue
 #pragma unroll
@@ -226,18 +256,20 @@ __device__ __forceinline__ double wide_rows(const HvArgs &a, const uint16_t *rt,
             if (g >= nblk) break;
             const uint32_t au = ul.alpha[g];
             const T xv = xsrc[g * cdn + rd];
-            T v = acc[g] + (ul.e[g] + ed + u_energy<T>(au & ad, a)) * xv;
-#pragma unroll
-            for (int u = 0; u < kUpPre; ++u) v += upc[g][u] * upv[g][u];
+            const T dg = ul.e[g] + ed + u_energy<T>(au & ad, a);
+            T v = fma_t(dg, xv, a.t_uniform ? (T)a.bamp[0] * acc[g] : acc[g]);
             const uint32_t n = ul.cnt[g];
+#pragma unroll
+            for (int u = 0; u < kUpPre; ++u)
+                if (u < (int)n) v = fma_t(upc[g][u], upv[g][u], v);
             for (uint32_t h = kUpPre; h < n; ++h)
-                v += ul.coef[g * nb + h] * x[sc.off + (uint64_t)ul.tgt[g * nb + h] * cdn + rd];
+                v = fma_t(ul.coef[g * nb + h], x[sc.off + (uint64_t)ul.tgt[g * nb + h] * cdn + rd], v);
             const uint64_t row = base + (uint64_t)g * cdn + rd;
             if constexpr (LZ) {
-                T u = (T)a.ep.c1[tl.sector] * v;
-                if (a.ep.c2) u -= (T)a.ep.c2[tl.sector] * pv[g];
+                const T u = lz_out(v, (T)a.ep.c1[tl.sector], a.ep.c2 ? (T)a.ep.c2[tl.sector] : (T)0, pv[g],
+                                   a.ep.c2 != nullptr);
                 out[row] = u;
-                dot += (double)xv * (double)u;
+                dot = __builtin_fma((double)xv, (double)u, dot);
             } else {
                 out[row] = v;
             }
@@ -364,25 +396,28 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
                 const T ed = (T)a.hs_energy[sc.hs_dn + rd];
                 const uint32_t au = up_alpha[g];
                 const T xv = xs[e];
-                T v = (up_e[g] + ed + u_energy<T>(au & ad, a)) * xv;
+                T acc = 0;
                 for (int b = 0; b < nb; ++b) {
                     const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
                     if (((ad >> bi) ^ (ad >> bj)) & 1) {
                         const uint32_t rr = rank_half<NCH>(ad ^ a.bmask[b], rt, a);
-                        const T c = (__popc(ad & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
-                        v += c * xs[g * cdn + rr];
+                        const T mag = a.t_uniform ? (T)1 : (T)a.bamp[b];
+                        const T c = (__popc(ad & a.bbetw[b]) & 1) ? mag : -mag;
+                        acc = fma_t(c, xs[g * cdn + rr], acc);
                     }
                 }
+                const T dg = up_e[g] + ed + u_energy<T>(au & ad, a);
+                T v = fma_t(dg, xv, a.t_uniform ? (T)a.bamp[0] * acc : acc);
 #pragma unroll
                 for (int u = 0; u < kUpPre; ++u)
-                    if (u < (int)n) v += up_coef[g * nb + u] * upv[u];
+                    if (u < (int)n) v = fma_t(up_coef[g * nb + u], upv[u], v);
                 for (uint32_t h = kUpPre; h < n; ++h)
-                    v += up_coef[g * nb + h] * x[sc.off + (uint64_t)up_tgt[g * nb + h] * cdn + rd];
+                    v = fma_t(up_coef[g * nb + h], x[sc.off + (uint64_t)up_tgt[g * nb + h] * cdn + rd], v);
                 if constexpr (LZ) {
-                    T u = (T)a.ep.c1[tl.sector] * v;
-                    if (a.ep.c2) u -= (T)a.ep.c2[tl.sector] * pv;
+                    const T u = lz_out(v, (T)a.ep.c1[tl.sector], a.ep.c2 ? (T)a.ep.c2[tl.sector] : (T)0, pv,
+                                       a.ep.c2 != nullptr);
                     out[row] = u;
-                    dot += (double)xv * (double)u;
+                    dot = __builtin_fma((double)xv, (double)u, dot);
                 } else {
                     out[row] = v;
                 }
@@ -397,67 +432,74 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
 
 // ------------------------------------------------------------------------
 // alpha_dn-stationary kernel.  A workgroup of kRowsBlock lanes sweeps a
-// contiguous run of tiles of one sector (or a few small sectors).  Each lane
-// owns fixed spin-down configurations (R of them, or one per (block, alpha_dn)
-// pair when C_dn is small); their down-hop targets are ranked once per run
-// (staggered lookup) and kept in registers as a compacted list in bond order,
-// so every alpha_up block of the run reuses them: per row and hop only one LDS
-// gather and one FMA remain.  The x rows of the next tile are loaded into
-// registers while the current tile computes and then written to the other
-// half of a double-buffered LDS tile; the next tile's up-hop targets are
-// ranked by 16-lane groups (one lane per bond, ballot compaction in bond
-// order).  Summation order per row is the same as in the tile kernel.
+// contiguous run of tiles (alpha_up blocks of one sector, or a few small
+// sectors).  Lane t owns fixed spin-down configurations of the sector: rows
+// t + r kRowsBlock (row slot r < R) of each alpha_up block, or one
+// (block, alpha_dn) pair when C_dn is small.
+//  * down-hops: the targets of an alpha_dn depend on alpha_dn alone.  They are
+//    ranked once per launch shape (staggered lookup, hv_lists_kernel) into a
+//    list per alpha_dn in bond order of 16-bit LDS byte offsets: the tile's x
+//    rows are staged twice, as x and as -x, and the offset selects the copy
+//    that carries the hop's fermion sign, so a down hop costs one LDS gather
+//    and one add.  Lists are padded with the offset of a zero stored after
+//    every block; the trip count of a row slot is the wave's longest list.
+//  * up-hops: alpha_up is uniform across a block; its targets are ranked once
+//    per tile (one lane per bond, ballot compaction in bond order) and read
+//    into scalar registers, so each gather is a scalar base plus the lane's
+//    offset.
+//  * pipelining: the global loads of row slot r + 1 (up-hop rows, the list,
+//    the alpha_dn pattern and energy, the epilogue operand) are issued before
+//    the LDS work of slot r, and the next tile's x rows are copied straight
+//    into the other half of a double-buffered LDS tile while this one
+//    computes.
+// Tiles are visited in the XCD-binned order of the tile kernel.  Per row the
+// terms are summed in the same order and with the same fused operations as in
+// the tile kernel, so both give bitwise identical products.
 // ------------------------------------------------------------------------
-// alpha_dn-stationary kernel.  Each lane owns fixed spin-down configurations
-// of the sector (R of them, or one (block, alpha_dn) pair when C_dn is small)
-// and ranks their down-hop targets once (staggered lookup); the targets stay
-// in registers as a list in bond order, padded with a pointer to a zero in
-// LDS, so every alpha_up block the workgroup visits reuses them: per row and
-// hop one LDS gather and one FMA remain, with no branches.  Up-hop targets
-// of a block are uniform: they are ranked once per tile (one lane per bond,
-// ballot compaction in bond order) and read into scalar registers, so each
-// up-hop gather is a scalar base plus the lane's offset.  The next tile's x
-// rows are loaded into registers while the current tile computes and then
-// stored to the other half of a double-buffered LDS tile.  Tiles are visited
-// in the XCD-binned order of the tile kernel.  Per row the terms are summed in
-// the same order as in the tile kernel, so both give identical results.
 constexpr int kRowsBlock = 1024;
-constexpr int kRowsNB = 16;    // bonds
-constexpr int kRowsMaxG = 64;  // alpha_up blocks per tile when C_dn is small
-constexpr int kRowsMaxR = 4;   // alpha_dn per lane, so C_dn <= 4096
-constexpr int kUpMax = 8;      // up-hop gathers in flight per row (more run in a tail loop)
+constexpr int kRowsNB = 16;           // bonds
+constexpr int kRowsMaxG = 64;         // alpha_up blocks per tile when C_dn is small
+constexpr int kRowsMaxR = 4;          // alpha_dn per lane
+constexpr int kUpMax = 8;             // up-hop gathers in flight per row (more run in a tail loop)
+constexpr int kRowsDownFixed = 12;    // down-hop entries summed without a branch (padding adds zeros)
+constexpr uint32_t kRowsMaxX = 4096;  // staged elements per tile (blocks of C_dn + 1): offsets fit 16 bits
+static_assert(kRowsMaxX <= (uint32_t)(kRowsMaxR * kRowsBlock), "R slots cover a block");
 
-// LDS layout: rank table | amplitudes | reduction scratch | two buffers, each
-// x rows (+ one zero) | up-hop targets | coefficients | alpha_up | energies |
-// counts.  Buffer b starts at buf0 + b * bstride.
+// LDS layout: rank table | bond amplitudes | on-site U | reduction scratch |
+// two buffers.
+// A buffer holds the tile's blocks with stride C_dn + 1 (x rows, then a zero)
+// from byte 0, the negated rows at byte cs, then up-hop targets |
+// coefficients | alpha_up | energies | counts for up to gmax blocks.
 struct RowsLds {
-    size_t rt, amp, red, buf0, bstride, xs, ut, uc, ua, ue, un, total;
+    size_t rt, amp, ul, red, buf0, bstride, cs, ut, uc, ua, ue, un, total;
 };
 
-__host__ __device__ inline RowsLds rows_lds_layout(uint32_t rtab_entries, uint32_t xcap, size_t tsz) {
+__host__ __device__ inline RowsLds rows_lds_layout(uint32_t rtab_entries, uint32_t xcap, uint32_t gmax,
+                                                   size_t tsz) {
     auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
     RowsLds L{};
     size_t o = 0;
     L.rt = o;
     o += r16((size_t)rtab_entries * 2);
     L.amp = o;
-    o += r16(2 * kRowsNB * tsz);
+    o += r16(kRowsNB * tsz);
+    L.ul = o;
+    o += r16(kMaxSites * tsz);
     L.red = o;
     o += 32 * sizeof(double);
     L.buf0 = o;
-    size_t b = 0;
-    L.xs = b;
-    b += r16((size_t)(xcap + 1) * tsz);
+    L.cs = r16((size_t)xcap * tsz);
+    size_t b = 2 * L.cs;
     L.ut = b;
-    b += r16((size_t)kRowsMaxG * kRowsNB * 4);
+    b += r16((size_t)gmax * kRowsNB * 4);
     L.uc = b;
-    b += r16((size_t)kRowsMaxG * kRowsNB * tsz);
+    b += r16((size_t)gmax * kRowsNB * tsz);
     L.ua = b;
-    b += r16(kRowsMaxG * 4);
+    b += r16((size_t)gmax * 4);
     L.ue = b;
-    b += r16(kRowsMaxG * tsz);
+    b += r16((size_t)gmax * tsz);
     L.un = b;
-    b += r16(kRowsMaxG * 4);
+    b += r16((size_t)gmax * 4);
     L.bstride = b;
     L.total = o + 2 * b;
     return L;
@@ -484,43 +526,91 @@ __device__ __forceinline__ T uniform_val(T v) {
     }
 }
 
+// Staged-row byte offset of down-hop target rr (negated copy for an even
+// number of fermions between the bond's sites, i.e. coefficient -t).
+__device__ __forceinline__ uint32_t rows_entry(uint32_t rr, bool odd, uint32_t tsz, uint32_t cs) {
+    return rr * tsz + (odd ? 0u : cs);
+}
+
+// Down-hop lists of one rows-kernel sector: row rd of `lists` holds the
+// entries of alpha_dn number rd (kRowsNB - 1 of them, 16-bit offsets two per
+// word when every bond has the same amplitude, else one per word with the bond
+// in the high half), padded with the offset of the block's zero, and the list
+// length in the last entry.
+template <bool UT>
+__global__ void __launch_bounds__(256) hv_lists_kernel(HvArgs a, uint32_t hs_dn, uint32_t cdn, uint32_t tsz,
+                                                       uint32_t cs, uint32_t *lists) {
+    const uint32_t rd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rd >= cdn) return;
+    constexpr int kWords = UT ? kRowsNB / 2 : kRowsNB;
+    const uint32_t ad = a.hs_states[hs_dn + rd];
+    const uint32_t zero = cdn * tsz;
+    uint32_t w[kWords];
+    for (int u = 0; u < kWords; ++u) w[u] = UT ? (zero | (zero << 16)) : zero;
+    uint32_t n = 0;
+    for (int b = 0; b < a.nb; ++b) {
+        const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+        if (!(((ad >> bi) ^ (ad >> bj)) & 1)) continue;
+        const uint32_t rr = rank_half<0>(ad ^ a.bmask[b], a.rtab, a);
+        uint32_t e = rows_entry(rr, __popc(ad & a.bbetw[b]) & 1, tsz, cs);
+        if constexpr (UT) {
+            const int wd = n >> 1, sh = (n & 1) * 16;
+            w[wd] = (w[wd] & ~(0xFFFFu << sh)) | (e << sh);
+        } else {
+            w[n] = e | ((uint32_t)b << 16);
+        }
+        ++n;
+    }
+    // the last entry holds the length (at most kRowsNB - 1 bonds in this mode)
+    if constexpr (UT) w[kWords - 1] = (w[kWords - 1] & 0xFFFFu) | (n << 16);
+    else w[kWords - 1] = n;
+    for (int u = 0; u < kWords; ++u) lists[(size_t)rd * kWords + u] = w[u];
+}
+
+// On-site U energy of a doubly occupied pattern, as u_energy but with the
+// site values read from LDS (same order of summation).
 template <class T>
-__device__ __forceinline__ void rows_uplists(const HvArgs &a, const uint16_t *rt, const HvTile &tl,
-                                             const HvSector &sc, unsigned char *bb, const RowsLds &LL) {
+__device__ __forceinline__ T rows_u_energy(uint32_t both, const HvArgs &a, const T *ul) {
+    if (a.U_uniform) return (T)(a.U0 * (double)__popc(both));
+    T e = 0;
+    uint32_t m = both & a.Umask;
+    while (m) {
+        const int i = __ffs(m) - 1;
+        m &= m - 1;
+        e += ul[i];
+    }
+    return e;
+}
+
+// Up-hop lists of a tile's blocks into buffer bb: lane t ranks bond t % 16 of
+// block t / 16 (16-lane groups stay inside a wave) and the hops are compacted
+// in bond order with a ballot.  au, eu: the block's alpha_up and its energy,
+// loaded ahead by the caller.
+template <class T>
+__device__ __forceinline__ void rows_uplists(const HvArgs &a, const uint16_t *rt, uint32_t nblk, uint32_t au,
+                                             T eu, unsigned char *bb, const RowsLds &LL) {
     uint32_t *ut = reinterpret_cast<uint32_t *>(bb + LL.ut);
     T *uc = reinterpret_cast<T *>(bb + LL.uc);
     uint32_t *ua = reinterpret_cast<uint32_t *>(bb + LL.ua);
     T *ue = reinterpret_cast<T *>(bb + LL.ue);
     uint32_t *un = reinterpret_cast<uint32_t *>(bb + LL.un);
-    // lane t: block g = t / 16, bond b = t % 16 (16-lane groups stay inside a wave)
     const uint32_t t = threadIdx.x;
     const uint32_t g = t >> 4, b = t & 15;
     bool hop = false;
     uint32_t tgt = 0;
     T coef = 0;
-    if (g < tl.nblk) {
-        const uint32_t hi = sc.hs_up + tl.rup0 + g;
-        const uint32_t au = a.hs_states[hi];
+    if (g < nblk) {
         if ((int)b < a.nb) {
             const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
             hop = ((au >> bi) ^ (au >> bj)) & 1;
             if (hop) {
-                const uint32_t beta = au ^ a.bmask[b];
-                uint32_t r = 0;
-                int np = 0;
-                const uint32_t cm = (1u << a.k) - 1;
-                for (int c = 0; c < a.nch; ++c) {
-                    const uint32_t ch = (beta >> (c * a.k)) & cm;
-                    r += rt[((uint32_t)(a.rowoff[c] + np) << a.k) + ch];
-                    np += __popc(ch);
-                }
-                tgt = r;
+                tgt = rank_half<0>(au ^ a.bmask[b], rt, a);
                 coef = (__popc(au & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
             }
         }
         if (b == 0) {
             ua[g] = au;
-            ue[g] = (T)a.hs_energy[hi];
+            ue[g] = eu;
         }
     }
     const unsigned long long bal = __ballot(hop);
@@ -532,25 +622,144 @@ __device__ __forceinline__ void rows_uplists(const HvArgs &a, const uint16_t *rt
         ut[g * kRowsNB + pos] = tgt;
         uc[g * kRowsNB + pos] = coef;
     }
-    if (b == 0 && g < tl.nblk) un[g] = (uint32_t)__popcll(bal & grp);
+    if (b == 0 && g < nblk) un[g] = (uint32_t)__popcll(bal & grp);
+}
+
+// Staging of a tile's x rows on the direct global-to-LDS path (no registers):
+// block g (C_dn rows) goes to byte g (C_dn + 1) sizeof(T) of the buffer in
+// 256-byte chunks, one wave instruction each.  Each wave then writes the
+// negated copy of its own chunks once its loads have landed, and the zero
+// after every block, so only the end-of-tile barrier is needed.
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+template <class T>
+__device__ __forceinline__ void rows_stage_issue(const T *src, unsigned char *bb, uint32_t nblk, uint32_t cdn) {
+    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t bytes = cdn * (uint32_t)sizeof(T);
+    const uint32_t nch = (bytes + 255) >> 8;
+    for (uint32_t j = w; j < nblk * nch; j += kRowsBlock / 64) {
+        const uint32_t g = j / nch, c = j - g * nch;
+        const uint32_t off = (c << 8) + l * 4;
+        if (off < bytes)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned char *>(src + (size_t)g * cdn) + off,
+                                             (lds_ptr_t)(bb + g * (bytes + (uint32_t)sizeof(T)) + (c << 8)), 4, 0,
+                                             0);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void rows_stage_finish(unsigned char *bb, size_t cs, uint32_t nblk, uint32_t cdn) {
+    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t bytes = cdn * (uint32_t)sizeof(T);
+    const uint32_t nch = (bytes + 255) >> 8;
+    // the sign is the top bit of each element: of every odd dword for fp64
+    const uint32_t flip = (sizeof(T) == 4 || (l & 1)) ? 0x80000000u : 0u;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's chunks have landed
+    for (uint32_t j = w; j < nblk * nch; j += kRowsBlock / 64) {
+        const uint32_t g = j / nch, c = j - g * nch;
+        const uint32_t off = g * (bytes + (uint32_t)sizeof(T)) + (c << 8) + l * 4;
+        if ((c << 8) + l * 4 < bytes) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(bb + off);
+            *reinterpret_cast<uint32_t *>(bb + cs + off) = v ^ flip;
+        }
+    }
+    if (threadIdx.x < nblk) reinterpret_cast<T *>(bb + threadIdx.x * (bytes + (uint32_t)sizeof(T)))[cdn] = (T)0;
+}
+
+// Sum of the down-hop terms of one row: the list entries (byte offsets from
+// xb) in groups of four; the groups past kRowsDownFixed entries are skipped
+// when they are past the end of every list of the wave.  Uniform amplitude: the signed x values are summed (the
+// caller scales by t); otherwise each is weighted by its bond's amplitude.
+template <class T, bool UT, int W>
+__device__ __forceinline__ T rows_down(const uint32_t (&hl)[W], const unsigned char *xb, const T *amp,
+                                       bool valid) {
+    const uint32_t n = valid ? (UT ? hl[W - 1] >> 16 : hl[W - 1]) : 0u;
+    T acc = 0;
+#pragma unroll
+    for (int u0 = 0; u0 < kRowsNB - 1; u0 += 4) {
+        // the first groups run unconditionally (padding reads the zero): a
+        // branch there would let the compiler sink the list load into it
+        if (u0 < kRowsDownFixed || (uint32_t)u0 < n) {
+            constexpr int kQ = 4;
+            T v[kQ];
+            T c[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int u = u0 + q;
+                if (u < kRowsNB - 1) {
+                    uint32_t e;
+                    if constexpr (UT) e = (hl[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu;
+                    else e = hl[u];
+                    v[q] = *reinterpret_cast<const T *>(xb + (e & 0xFFFFu));
+                    if constexpr (!UT) c[q] = amp[e >> 16];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                if (u0 + q < kRowsNB - 1) {
+                    if constexpr (UT) acc += v[q];
+                    else acc = fma_t(c[q], v[q], acc);
+                }
+            }
+        }
+    }
+    return acc;
+}
+
+template <int W>
+__device__ __forceinline__ void rows_load_list(const uint32_t *row, uint32_t (&hl)[W]) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(row);
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q) {
+        const uint4 v = p[q];
+        hl[4 * q] = v.x;
+        hl[4 * q + 1] = v.y;
+        hl[4 * q + 2] = v.z;
+        hl[4 * q + 3] = v.w;
+    }
+}
+
+// Uniform copy of a rows-kernel tile descriptor (RowsTileDesc).
+struct RowsTile {
+    uint64_t base, soff;
+    uint32_t cdn, gp, nblk, hs_up0, hs_dn, loff, sector, slot;
+};
+
+__device__ __forceinline__ void rows_desc_load(const RowsTileDesc *d, uint32_t t, uint4 (&q)[2]) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(d + t);
+    q[0] = p[0];
+    q[1] = p[1];
+}
+
+__device__ __forceinline__ RowsTile rows_desc_uniform(const uint4 (&q)[2]) {
+    auto u = [](uint32_t v) { return __builtin_amdgcn_readfirstlane(v); };
+    RowsTile r;
+    r.base = ((uint64_t)u(q[0].y) << 32) | u(q[0].x);
+    r.soff = ((uint64_t)u(q[0].w) << 32) | u(q[0].z);
+    const uint32_t w0 = u(q[1].x), w1 = u(q[1].y), w2 = u(q[1].z);
+    r.cdn = w0 & 0xFFF;
+    r.gp = (w0 >> 12) & 0xFF;
+    r.nblk = w0 >> 20;
+    r.hs_up0 = w1 & 0xFFFF;
+    r.hs_dn = w1 >> 16;
+    r.loff = w2 & 0xFFFF;
+    r.sector = w2 >> 16;
+    r.slot = u(q[1].w);
+    return r;
 }
 
 template <class T, bool LZ, int R, bool UT>
 __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const RowsLds LL = rows_lds_layout(a.rtab_entries, a.xcap, sizeof(T));
+    const RowsLds LL = rows_lds_layout(a.rtab_entries, a.xcap, a.rgmax, sizeof(T));
     uint16_t *rt = reinterpret_cast<uint16_t *>(smem + LL.rt);
     T *amp = reinterpret_cast<T *>(smem + LL.amp);
+    T *ul = reinterpret_cast<T *>(smem + LL.ul);
     double *red = reinterpret_cast<double *>(smem + LL.red);
     for (uint32_t i = threadIdx.x; i < a.rtab_entries; i += blockDim.x) rt[i] = a.rtab[i];
-    if (threadIdx.x < 2 * (uint32_t)a.nb) {
-        const int b = threadIdx.x >> 1;
-        amp[threadIdx.x] = (threadIdx.x & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
-    }
-    if (threadIdx.x < 2) {  // the zero every non-hop entry points at
-        T *xz = reinterpret_cast<T *>(smem + LL.buf0 + threadIdx.x * LL.bstride + LL.xs);
-        xz[a.xcap] = (T)0;
-    }
+    if (threadIdx.x < (uint32_t)kRowsNB)
+        amp[threadIdx.x] = threadIdx.x < (uint32_t)a.nb ? (T)a.bamp[threadIdx.x] : (T)0;
+    if (threadIdx.x < (uint32_t)kMaxSites) ul[threadIdx.x] = (T)a.U[threadIdx.x];
 
     const T *x = static_cast<const T *>(a.x);
     T *out = static_cast<T *>(a.out);
@@ -574,124 +783,77 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     if (t_cur >= t_end) return;
 
     const int tid = threadIdx.x;
-    constexpr int kPer = UT ? 2 : 1;  // entries per register
-    constexpr int kWords = kRowsNB / kPer;
-    uint32_t hl[R][kWords];
-    uint32_t ad[R];
-    T ed[R];
-    int wmax = 0;
-    uint32_t cur_sector = 0xFFFFFFFFu;
+    constexpr int kWords = UT ? kRowsNB / 2 : kRowsNB;
+    const uint32_t *lists = static_cast<const uint32_t *>(a.lists);
+    const RowsTileDesc *desc = a.rdesc;
+    const T tu = (T)a.bamp[0];
+    const uint32_t ug = (uint32_t)tid >> 4;  // block of this lane in the up-hop ranking
+    const bool has_p = LZ && a.ep.c2;
 
-    __syncthreads();  // rank table, amplitudes and zeros in LDS
+    // Tile descriptors are loaded two tiles ahead and the per-tile scalars
+    // (flags, epilogue coefficients, alpha_up of the ranking lanes) one tile
+    // ahead, so no dependent load sits at the head of a tile.
+    uint4 qc[2], qn[2];
+    rows_desc_load(desc, t_cur, qc);
+    rows_desc_load(desc, t_cur + t_step < t_end ? t_cur + t_step : t_cur, qn);
+    int act_c;
+    T c1_c, c2_c;
+    __syncthreads();  // rank table, amplitudes and U in LDS
     {
-        const HvTile tl = a.tiles[t_cur];
-        const HvSector sc = a.secs[tl.sector];
+        const RowsTile c = rows_desc_uniform(qc);
         unsigned char *bb = smem + LL.buf0;
-        T *xs = reinterpret_cast<T *>(bb + LL.xs);
-        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
-        const uint32_t rows = tl.nblk * sc.cdn;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) xs[e] = x[base + e];
-        rows_uplists<T>(a, rt, tl, sc, bb, LL);
+        rows_stage_issue<T>(x + c.base, bb, c.nblk, c.cdn);
+        const uint32_t au = ug < c.nblk ? a.hs_states[c.hs_up0 + ug] : 0u;
+        const T eu = ug < c.nblk ? (T)a.hs_energy[c.hs_up0 + ug] : (T)0;
+        act_c = a.ep.active ? a.ep.active[c.sector] : 1;
+        c1_c = LZ ? (T)a.ep.c1[c.sector] : (T)1;
+        c2_c = has_p ? (T)a.ep.c2[c.sector] : (T)0;
+        rows_uplists<T>(a, rt, c.nblk, au, eu, bb, LL);
+        rows_stage_finish<T>(bb, LL.cs, c.nblk, c.cdn);
     }
     __syncthreads();
 
     for (int buf = 0; t_cur < t_end; t_cur += t_step, buf ^= 1) {
-        const HvTile tl = a.tiles[t_cur];
-        const HvSector sc = a.secs[tl.sector];
-        const uint32_t cdn = sc.cdn;
-        const uint64_t base = sc.off + (uint64_t)tl.rup0 * cdn;
-        unsigned char *bb = smem + LL.buf0 + (size_t)buf * LL.bstride;
-        const T *xs = reinterpret_cast<const T *>(bb + LL.xs);
+        const RowsTile c = rows_desc_uniform(qc);
+        const uint32_t t_next = t_cur + t_step;
+        const bool has_next = t_next < t_end;
+        uint4 qnn[2];
+        rows_desc_load(desc, t_next + t_step < t_end ? t_next + t_step : t_cur, qnn);
+        const bool active = __builtin_amdgcn_readfirstlane(act_c) != 0;
+        const T c1 = uniform_val(c1_c), c2 = uniform_val(c2_c);
+
+        // the next tile's x rows go straight into the other buffer (free since
+        // the last barrier) while this tile computes; its scalars are loaded
+        unsigned char *nb2 = smem + LL.buf0 + (size_t)(buf ^ 1) * LL.bstride;
+        RowsTile n{};
+        uint32_t au_n = 0;
+        T eu_n = 0;
+        if (has_next) {
+            n = rows_desc_uniform(qn);
+            rows_stage_issue<T>(x + n.base, nb2, n.nblk, n.cdn);
+            if (ug < n.nblk) {
+                au_n = a.hs_states[n.hs_up0 + ug];
+                eu_n = (T)a.hs_energy[n.hs_up0 + ug];
+            }
+            act_c = a.ep.active ? a.ep.active[n.sector] : 1;
+            c1_c = LZ ? (T)a.ep.c1[n.sector] : (T)1;
+            c2_c = has_p ? (T)a.ep.c2[n.sector] : (T)0;
+        }
+
+        const uint32_t cdn = c.cdn;
+        const uint64_t base = c.base;
+        const unsigned char *bb = smem + LL.buf0 + (size_t)buf * LL.bstride;
         const uint32_t *ut = reinterpret_cast<const uint32_t *>(bb + LL.ut);
         const T *uc = reinterpret_cast<const T *>(bb + LL.uc);
         const uint32_t *ua = reinterpret_cast<const uint32_t *>(bb + LL.ua);
         const T *ue = reinterpret_cast<const T *>(bb + LL.ue);
         const uint32_t *un = reinterpret_cast<const uint32_t *>(bb + LL.un);
-
-        // new sector: this lane's alpha_dn and their down-hop targets
-        if (tl.sector != cur_sector) {
-            cur_sector = tl.sector;
-            int mx = 0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                int g, rd;
-                if (sc.gp > 1) {
-                    g = tid / (int)cdn;
-                    rd = tid - g * (int)cdn;
-                } else {
-                    g = 0;
-                    rd = tid + r * kRowsBlock;
-                }
-                const bool ok = (r == 0 || sc.gp == 1) && rd < (int)cdn && g < (int)sc.gp;
-                ad[r] = ok ? a.hs_states[sc.hs_dn + rd] : 0u;
-                ed[r] = ok ? (T)a.hs_energy[sc.hs_dn + rd] : (T)0;
-                // index of the LDS zero relative to this lane's block rows
-                const uint32_t zero = ok ? a.xcap - (uint32_t)g * cdn : 0u;
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int u = 0; u < kWords; ++u) hl[r][u] = UT ? (zero | (zero << 16)) : zero;
-#pragma unroll
-                for (int b = 0; b < kRowsNB; ++b) {
-                    const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
-                    const bool hop = ok && b < a.nb && (((ad[r] >> bi) ^ (ad[r] >> bj)) & 1);
-                    uint32_t e = 0;
-                    if (hop) {
-                        const uint32_t beta = ad[r] ^ a.bmask[b];
-                        uint32_t rr = 0;
-                        int np = 0;
-                        const uint32_t cm = (1u << a.k) - 1;
-                        for (int c = 0; c < a.nch; ++c) {
-                            const uint32_t ch = (beta >> (c * a.k)) & cm;
-                            rr += rt[((uint32_t)(a.rowoff[c] + np) << a.k) + ch];
-                            np += __popc(ch);
-                        }
-                        const uint32_t sg = __popc(ad[r] & a.bbetw[b]) & 1;
-                        e = UT ? (rr | (sg << 15)) : (rr | ((uint32_t)b << 16) | (sg << 21));
-                    }
-                    // append in bond order without indexing registers by a runtime value
-#pragma unroll
-                    for (int u = 0; u < kRowsNB; ++u) {
-                        const int wd = u / kPer, sh = (u % kPer) * 16;
-                        const uint32_t put = UT ? ((hl[r][wd] & ~(0xFFFFu << sh)) | (e << sh)) : e;
-                        hl[r][wd] = (hop && cnt == (uint32_t)u) ? put : hl[r][wd];
-                    }
-                    cnt += hop ? 1u : 0u;
-                }
-                mx = (int)cnt > mx ? (int)cnt : mx;
-            }
-            for (int o = 32; o > 0; o >>= 1) {  // wave-uniform trip count of the hop loop
-                const int v = __shfl_xor(mx, o, 64);
-                mx = v > mx ? v : mx;
-            }
-            wmax = mx;
-        }
-
-        // prefetch the next tile's x rows into registers
-        constexpr int kPre = 4;
-        T pre[kPre];
-        uint32_t nrows_next = 0;
-        const uint32_t t_next = t_cur + t_step;
-        const bool has_next = t_next < t_end;
-        if (has_next) {
-            const HvTile tn = a.tiles[t_next];
-            const HvSector sn = a.secs[tn.sector];
-            nrows_next = tn.nblk * sn.cdn;
-            const uint64_t nbase = sn.off + (uint64_t)tn.rup0 * sn.cdn;
-#pragma unroll
-            for (int j = 0; j < kPre; ++j) {
-                const uint32_t e = tid + j * kRowsBlock;
-                pre[j] = e < nrows_next ? x[nbase + e] : (T)0;
-            }
-        }
-
-        const bool active = !a.ep.active || a.ep.active[tl.sector];
-        const T c1 = LZ ? (T)a.ep.c1[tl.sector] : (T)1;
-        const T c2 = (LZ && a.ep.c2) ? (T)a.ep.c2[tl.sector] : (T)0;
-        const T tu = (T)a.bamp[0];
+        const uint32_t *slists = lists + (size_t)c.loff * kWords;
+        const T *xsec = x + c.soff;
         double dot = 0.0;
         if (active) {
-            if (sc.gp == 1) {
-                // one alpha_up block per tile: its data is uniform, hold it in scalars
+            if (c.gp == 1) {
+                // One alpha_up block per tile: its data is uniform, held in scalars.
                 const uint32_t nu = __builtin_amdgcn_readfirstlane(un[0]);
                 const uint32_t au = __builtin_amdgcn_readfirstlane(ua[0]);
                 const T eu = uniform_val(ue[0]);
@@ -699,104 +861,85 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 T cf[kUpMax];
 #pragma unroll
                 for (int h = 0; h < kUpMax; ++h) {
-                    const uint32_t tg = h < (int)nu ? __builtin_amdgcn_readfirstlane(ut[h]) : 0u;
-                    cf[h] = h < (int)nu ? uniform_val(uc[h]) : (T)0;
-                    src[h] = x + sc.off + (uint64_t)tg * cdn;
+                    const bool hh = h < (int)nu;
+                    src[h] = xsec + (uint64_t)(hh ? __builtin_amdgcn_readfirstlane(ut[h]) : 0u) * cdn;
+                    cf[h] = hh ? uniform_val(uc[h]) : (T)0;
                 }
+                T gx[2][kUpMax], gp_[2], ge[2];
+                uint32_t ga[2];
+                uint32_t hl[2][kWords];
+                // a fixed batch of loads per row slot (lanes past C_dn read row 0,
+                // hops past nu read row 0 of the sector with coefficient 0), so
+                // the wait for slot r leaves slot r + 1 in flight
+                const T *pp = has_p ? p : x;
+                auto gather = [&](int r, int s) {
+                    const int rd = tid + r * kRowsBlock;
+                    const int rc = rd < (int)cdn ? rd : 0;
+#pragma unroll
+                    for (int h = 0; h < kUpMax; ++h) gx[s][h] = src[h][rc];
+                    rows_load_list(slists + (size_t)rc * kWords, hl[s]);
+                    ga[s] = a.hs_states[c.hs_dn + rc];
+                    ge[s] = (T)a.hs_energy[c.hs_dn + rc];
+                    if constexpr (LZ) gp_[s] = pp[base + rc];
+                };
+                gather(0, 0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    const int s = r & 1;
+                    if (r + 1 < R) gather(r + 1, s ^ 1);
                     const int rd = tid + r * kRowsBlock;
-                    if (rd >= (int)cdn) continue;
-                    const uint64_t row = base + rd;
-                    T upv[kUpMax];
+                    const T acc = rows_down<T, UT>(hl[s], bb, amp, rd < (int)cdn);
+                    if (rd < (int)cdn) {
+                        const T xv = reinterpret_cast<const T *>(bb)[rd];
+                        const T dg = eu + ge[s] + rows_u_energy<T>(au & ga[s], a, ul);
+                        T v = fma_t(dg, xv, UT ? tu * acc : acc);
+                        // cf = 0 and gx = x[row 0] past nu: those terms add an exact zero
 #pragma unroll
-                    for (int h = 0; h < kUpMax; ++h) upv[h] = h < (int)nu ? src[h][rd] : (T)0;
-                    T pv = 0;
-                    if constexpr (LZ) {
-                        if (a.ep.c2) pv = p[row];
-                    }
-                    T acc = 0;
-#pragma unroll
-                    for (int u = 0; u < kRowsNB; ++u) {
-                        if (u < wmax) {
-                            uint32_t idx;
-                            T c;
-                            if constexpr (UT) {
-                                const uint32_t e = (hl[r][u / kPer] >> ((u % kPer) * 16)) & 0xFFFFu;
-                                idx = e & 0x7FFFu;
-                                c = (e >> 15) ? tu : -tu;
-                            } else {
-                                const uint32_t e = hl[r][u];
-                                idx = e & 0xFFFFu;
-                                c = amp[((e >> 16) & 31) * 2 + (e >> 21)];
-                            }
-                            acc += c * xs[idx];
+                        for (int h = 0; h < kUpMax; ++h) v = fma_t(cf[h], gx[s][h], v);
+                        for (uint32_t h = kUpMax; h < nu; ++h)
+                            v = fma_t(uniform_val(uc[h]),
+                                      xsec[(uint64_t)__builtin_amdgcn_readfirstlane(ut[h]) * cdn + rd], v);
+                        const uint64_t row = base + rd;
+                        if constexpr (LZ) {
+                            const T uu = lz_out(v, c1, c2, gp_[s], has_p);
+                            out[row] = uu;
+                            dot = __builtin_fma((double)xv, (double)uu, dot);
+                        } else {
+                            out[row] = v;
                         }
-                    }
-                    const T xv = xs[rd];
-                    T v = acc + (eu + ed[r] + u_energy<T>(au & ad[r], a)) * xv;
-#pragma unroll
-                    for (int h = 0; h < kUpMax; ++h)
-                        if (h < (int)nu) v += cf[h] * upv[h];
-                    for (uint32_t h = kUpMax; h < nu; ++h) {
-                        const uint32_t tg = __builtin_amdgcn_readfirstlane(ut[h]);
-                        v += uniform_val(uc[h]) * x[sc.off + (uint64_t)tg * cdn + rd];
-                    }
-                    if constexpr (LZ) {
-                        T uu = c1 * v;
-                        if (a.ep.c2) uu -= c2 * pv;
-                        out[row] = uu;
-                        dot += (double)xv * (double)uu;
-                    } else {
-                        out[row] = v;
                     }
                 }
             } else {
-                // several small blocks per tile: block data per lane from LDS
+                // several small blocks per tile: block data per lane from LDS; the
+                // first kUpMax up-hop gathers are issued before the LDS work
                 const int g = tid / (int)cdn;
-                if (g < (int)tl.nblk && g < (int)sc.gp) {
+                if (g < (int)c.nblk && g < (int)c.gp) {
                     const int rd = tid - g * (int)cdn;
                     const uint64_t row = base + (uint64_t)g * cdn + rd;
                     const uint32_t nu = un[g];
-                    T upv[kUpMax];
+                    T gx[kUpMax];
 #pragma unroll
                     for (int h = 0; h < kUpMax; ++h)
-                        upv[h] = h < (int)nu ? x[sc.off + (uint64_t)ut[g * kRowsNB + h] * cdn + rd] : (T)0;
-                    T pv = 0;
-                    if constexpr (LZ) {
-                        if (a.ep.c2) pv = p[row];
-                    }
-                    const T *xr = xs + g * cdn;
-                    T acc = 0;
-#pragma unroll
-                    for (int u = 0; u < kRowsNB; ++u) {
-                        if (u < wmax) {
-                            uint32_t idx;
-                            T c;
-                            if constexpr (UT) {
-                                const uint32_t e = (hl[0][u / kPer] >> ((u % kPer) * 16)) & 0xFFFFu;
-                                idx = e & 0x7FFFu;
-                                c = (e >> 15) ? tu : -tu;
-                            } else {
-                                const uint32_t e = hl[0][u];
-                                idx = e & 0xFFFFu;
-                                c = amp[((e >> 16) & 31) * 2 + (e >> 21)];
-                            }
-                            acc += c * xr[idx];
-                        }
-                    }
-                    const T xv = xr[rd];
-                    T v = acc + (ue[g] + ed[0] + u_energy<T>(ua[g] & ad[0], a)) * xv;
+                        gx[h] = h < (int)nu ? xsec[(uint64_t)ut[g * kRowsNB + h] * cdn + rd] : (T)0;
+                    uint32_t hl[kWords];
+                    rows_load_list(slists + (size_t)rd * kWords, hl);
+                    const T pv = has_p ? p[row] : (T)0;
+                    const uint32_t adr = a.hs_states[c.hs_dn + rd];
+                    const T edr = (T)a.hs_energy[c.hs_dn + rd];
+                    const unsigned char *xb = bb + (size_t)g * (cdn + 1) * sizeof(T);
+                    const T acc = rows_down<T, UT>(hl, xb, amp, true);
+                    const T xv = reinterpret_cast<const T *>(xb)[rd];
+                    const T dg = ue[g] + edr + rows_u_energy<T>(ua[g] & adr, a, ul);
+                    T v = fma_t(dg, xv, UT ? tu * acc : acc);
 #pragma unroll
                     for (int h = 0; h < kUpMax; ++h)
-                        if (h < (int)nu) v += uc[g * kRowsNB + h] * upv[h];
+                        if (h < (int)nu) v = fma_t(uc[g * kRowsNB + h], gx[h], v);
                     for (uint32_t h = kUpMax; h < nu; ++h)
-                        v += uc[g * kRowsNB + h] * x[sc.off + (uint64_t)ut[g * kRowsNB + h] * cdn + rd];
+                        v = fma_t(uc[g * kRowsNB + h], xsec[(uint64_t)ut[g * kRowsNB + h] * cdn + rd], v);
                     if constexpr (LZ) {
-                        T uu = c1 * v;
-                        if (a.ep.c2) uu -= c2 * pv;
+                        const T uu = lz_out(v, c1, c2, pv, has_p);
                         out[row] = uu;
-                        dot += (double)xv * (double)uu;
+                        dot = __builtin_fma((double)xv, (double)uu, dot);
                     } else {
                         out[row] = v;
                     }
@@ -804,24 +947,19 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
             }
         }
         if (a.ep.partial) {
-            const double s = block_sum(dot, red);
-            if (threadIdx.x == 0) a.ep.partial[tl.slot] = active ? s : 0.0;
+            const double sum = block_sum(dot, red);
+            if (threadIdx.x == 0) a.ep.partial[c.slot] = active ? sum : 0.0;
         }
-        // the other buffer is free (its tile finished before the last barrier):
-        // store the prefetched rows and rank the next tile's up-hop targets
+        // next tile: up-hop targets, negated copy of the staged rows, zeros
         if (has_next) {
-            unsigned char *nb2 = smem + LL.buf0 + (size_t)(buf ^ 1) * LL.bstride;
-            T *xn = reinterpret_cast<T *>(nb2 + LL.xs);
-#pragma unroll
-            for (int j = 0; j < kPre; ++j) {
-                const uint32_t e = tid + j * kRowsBlock;
-                if (e < nrows_next) xn[e] = pre[j];
-            }
-            const HvTile tn = a.tiles[t_next];
-            const HvSector sn = a.secs[tn.sector];
-            rows_uplists<T>(a, rt, tn, sn, nb2, LL);
+            rows_uplists<T>(a, rt, n.nblk, au_n, eu_n, nb2, LL);
+            rows_stage_finish<T>(nb2, LL.cs, n.nblk, n.cdn);
         }
         __syncthreads();
+        qc[0] = qn[0];
+        qc[1] = qn[1];
+        qn[0] = qnn[0];
+        qn[1] = qnn[1];
     }
 }
 
@@ -881,6 +1019,9 @@ void fill_args(const mbr_hubbard *h, HvArgs &a, const void *x, void *out, const 
         if (u != a.U0) a.U_uniform = 0;
     }
     a.upcap = h->upcap;
+    a.lists = h->d_lists.p;
+    a.rgmax = h->rows_gmax;
+    a.t_uniform = h->t_uniform ? 1 : 0;
     a.maxblk = h->maxblk;
     a.ep = ep;
 }
@@ -888,7 +1029,7 @@ void fill_args(const mbr_hubbard *h, HvArgs &a, const void *x, void *out, const 
 template <class T, bool LZ, int R>
 mbr_status launch_rows_r(const mbr_hubbard *h, const HvArgs &a, unsigned grid, hipStream_t s) {
     auto kern = h->t_uniform ? hv_rows_kernel<T, LZ, R, true> : hv_rows_kernel<T, LZ, R, false>;
-    const size_t lds = rows_lds_layout(a.rtab_entries, a.xcap, sizeof(T)).total;
+    const size_t lds = rows_lds_layout(a.rtab_entries, a.xcap, a.rgmax, sizeof(T)).total;
     if (lds > 64 * 1024)
         MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -919,6 +1060,8 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
         a.binned = 0;
         if (ep.n_tiles == 0) return MBR_OK;
         if (h->hsec[ep.sector].rows) {
+            // the sector's tiles are the slot range starting at its first slot
+            a.rdesc = h->d_rdesc_slot.as<RowsTileDesc>() + h->hsec[ep.sector].slot0;
             a.xcap = h->rows_xcap;
             const unsigned grid = (unsigned)std::min<uint64_t>(ep.n_tiles, (uint64_t)h->rows_grid);
             if (ep.c1) return launch_rows<T, true>(h, a, grid, h->hsec[ep.sector].R, s);
@@ -932,7 +1075,7 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
     }
     if (!h->rows_tiles.empty()) {
         HvArgs ar = a;
-        ar.tiles = h->d_rows_tiles.as<HvTile>();
+        ar.rdesc = h->d_rdesc.as<RowsTileDesc>();
         ar.n_tiles = (uint32_t)h->rows_tiles.size();
         ar.binned = 1;
         for (int i = 0; i <= kXcd; ++i) ar.xoff[i] = h->rows_xoff[i];
@@ -985,6 +1128,33 @@ std::vector<uint32_t> balanced_ranges(const std::vector<HvTile> &tiles, const st
     return r;
 }
 
+// Down-hop lists of the rows kernel, one set per n_dn it serves (lrows rows in
+// all), ranked on the device with the launch shape's table.
+mbr_status build_lists(mbr_hubbard *h, uint32_t lrows, hipStream_t s) {
+    if (h->lists_ndn.empty()) return MBR_OK;
+    const uint32_t tsz = h->precision == MBR_F64 ? 8 : 4;
+    const uint32_t words = h->t_uniform ? kRowsNB / 2 : kRowsNB;
+    MBR_TRY(h->d_lists.alloc((size_t)lrows * words * 4));
+    HvArgs a{};
+    fill_args(h, a, nullptr, nullptr, HvEpilogue{});
+    const uint32_t cs =
+        (uint32_t)rows_lds_layout(a.rtab_entries, h->rows_xcap, h->rows_gmax, tsz).cs;
+    uint32_t row0 = 0;
+    for (size_t li = 0; li < h->lists_ndn.size(); ++li) {
+        const uint32_t nd = h->lists_ndn[li];
+        const uint32_t cdn = (uint32_t)binom(h->L, (int)nd);
+        uint32_t *lists = h->d_lists.as<uint32_t>() + (size_t)row0 * words;
+        const unsigned grid = (cdn + 255) / 256;
+        if (h->t_uniform)
+            hv_lists_kernel<true><<<grid, 256, 0, s>>>(a, h->hs_off[nd], cdn, tsz, cs, lists);
+        else
+            hv_lists_kernel<false><<<grid, 256, 0, s>>>(a, h->hs_off[nd], cdn, tsz, cs, lists);
+        MBR_HIP(hipGetLastError());
+        row0 += cdn;
+    }
+    return MBR_OK;
+}
+
 // Rebuild the rank table, tiles, work ranges and LDS budgets for (k, G, block).
 // G = 0 selects the alpha_dn-stationary kernel for every sector it supports.
 mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
@@ -1003,7 +1173,8 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     std::vector<HvSector> hsec;
     std::vector<HvTile> tiles, rows_tiles, other_tiles;
     uint64_t off = 0;
-    uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0;
+    uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0, rows_gmax = 1, lrows = 0;
+    std::vector<uint32_t> lists_ndn, lists_rows;
     int rows_R = 1;
     const uint32_t nbm = (uint32_t)std::max(1, h->nb);
     for (size_t si = 0; si < h->secs.size(); ++si) {
@@ -1013,7 +1184,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
         sc.cdn = (uint32_t)binom(L, h->secs[si].n_dn);
         sc.hs_up = h->hs_off[h->secs[si].n_up];
         sc.hs_dn = h->hs_off[h->secs[si].n_dn];
-        sc.rows = (G == 0 && sc.cdn <= (uint32_t)(kRowsMaxR * kRowsBlock) && h->nb <= kRowsNB) ? 1 : 0;
+        sc.rows = (G == 0 && sc.cdn + 1 <= kRowsMaxX && h->nb <= kRowsNB - 1) ? 1 : 0;
         uint32_t nblk;
         if (sc.rows) {
             sc.wide = 1;
@@ -1021,6 +1192,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             sc.gp = sc.cdn <= (uint32_t)kRowsBlock / 2 ? std::min<uint32_t>(kRowsMaxG, kRowsBlock / sc.cdn) : 1;
             sc.R = sc.gp > 1 ? 1 : (sc.cdn + kRowsBlock - 1) / kRowsBlock;
             rows_R = std::max(rows_R, (int)sc.R);
+            rows_gmax = std::max(rows_gmax, sc.gp);
             nblk = sc.gp;
         } else {
             sc.wide = sc.cdn >= kWideMin;
@@ -1044,7 +1216,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             t.nblk = std::min(nblk, sc.cup - r);
             t.slot = slot++;
             if (sc.rows) {
-                rows_xcap = std::max(rows_xcap, t.nblk * sc.cdn);
+                rows_xcap = std::max(rows_xcap, t.nblk * (sc.cdn + 1));
                 rows_tiles.push_back(t);
             } else {
                 if (sc.x_lds) xcap = std::max(xcap, t.nblk * sc.cdn);
@@ -1055,6 +1227,17 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             tiles.push_back(t);
         }
         sc.nslots = slot - sc.slot0;
+        if (sc.rows) {  // down-hop lists are shared by the sectors of one n_dn
+            const uint32_t nd = (uint32_t)h->secs[si].n_dn;
+            auto it = std::find(lists_ndn.begin(), lists_ndn.end(), nd);
+            const size_t li = (size_t)(it - lists_ndn.begin());
+            if (it == lists_ndn.end()) {
+                lists_ndn.push_back(nd);
+                lists_rows.push_back(lrows);
+                lrows += sc.cdn;
+            }
+            sc.loff = lists_rows[li];
+        }
         hsec.push_back(sc);
         off += (uint64_t)sc.cup * sc.cdn;
     }
@@ -1065,7 +1248,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     rows_grid -= rows_grid % kXcd;
     if (rows_grid < kXcd) rows_grid = kXcd;
     const std::vector<uint32_t> rr = balanced_ranges(rows_tiles, hsec, kXcd);
-    const size_t rows_lds = rows_lds_layout((uint32_t)((uint64_t)tab.nrows << k), rows_xcap, tsz).total;
+    const size_t rows_lds = rows_lds_layout((uint32_t)((uint64_t)tab.nrows << k), rows_xcap, rows_gmax, tsz).total;
     if (!rows_tiles.empty() && rows_lds > kLdsMax) MBR_FAIL(MBR_EUNSUPPORTED, "rows kernel needs %zu bytes of LDS", rows_lds);
     bool t_uniform = true;
     for (auto &b : h->bonds) t_uniform = t_uniform && b.t == h->bonds[0].t;
@@ -1086,10 +1269,35 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     h->maxblk = maxblk;
     h->rows_xcap = rows_xcap;
     h->rows_R = rows_R;
+    h->lists_ndn = lists_ndn;
+    h->rows_gmax = rows_gmax;
     h->rows_grid = rows_grid;
     h->t_uniform = t_uniform;
     MBR_TRY(upload(h->d_tiles, other_tiles.data(), other_tiles.size() * sizeof(HvTile), s));
-    MBR_TRY(upload(h->d_rows_tiles, rows_tiles.data(), rows_tiles.size() * sizeof(HvTile), s));
+    {
+        auto mk = [&](const HvTile &t) {
+            const HvSector &sc = hsec[t.sector];
+            RowsTileDesc d{};
+            d.base = sc.off + (uint64_t)t.rup0 * sc.cdn;
+            d.soff = sc.off;
+            d.w0 = sc.cdn | (sc.gp << 12) | (t.nblk << 20);
+            d.w1 = (sc.hs_up + t.rup0) | (sc.hs_dn << 16);
+            d.w2 = sc.loff | (t.sector << 16);
+            d.slot = t.slot;
+            return d;
+        };
+        for (auto &t : rows_tiles) {  // field widths of the packed descriptor
+            const HvSector &sc = hsec[t.sector];
+            if (sc.cdn > 0xFFF || sc.gp > 0xFF || t.nblk > 0xFFF || sc.hs_up + t.rup0 > 0xFFFF ||
+                sc.hs_dn > 0xFFFF || sc.loff > 0xFFFF || t.sector > 0xFFFF)
+                MBR_FAIL(MBR_EUNSUPPORTED, "rows-kernel tile descriptor out of range");
+        }
+        std::vector<RowsTileDesc> rd, rs;
+        for (auto &t : rows_tiles) rd.push_back(mk(t));
+        for (auto &t : tiles) rs.push_back(mk(t));
+        MBR_TRY(upload(h->d_rdesc, rd.data(), rd.size() * sizeof(RowsTileDesc), s));
+        MBR_TRY(upload(h->d_rdesc_slot, rs.data(), rs.size() * sizeof(RowsTileDesc), s));
+    }
     for (int b = 0; b <= kXcd; ++b) h->rows_xoff[b] = rr[b];
     MBR_TRY(upload(h->d_secs, h->hsec.data(), h->hsec.size() * sizeof(HvSector), s));
     h->lds_bytes = std::max(other_tiles.empty() ? 0 : lds_bytes_for(h, tsz), rows_tiles.empty() ? 0 : rows_lds);
@@ -1102,6 +1310,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     h->grid = device_cu_count() * per_cu;
     h->grid -= h->grid % kXcd;
     if (h->grid < kXcd) h->grid = kXcd;
+    MBR_TRY(build_lists(h, lrows, s));
     h->generation++;
     return MBR_OK;
 }

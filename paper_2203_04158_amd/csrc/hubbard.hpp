@@ -27,6 +27,7 @@ struct HvSector {
     uint32_t rows;    // handled by the alpha_dn-stationary kernel (1) or the tile kernel (0)
     uint32_t gp;      // rows kernel: alpha_up blocks per tile (lanes over (block, alpha_dn))
     uint32_t R;       // rows kernel: alpha_dn values per lane
+    uint32_t loff;    // rows kernel: first down-hop list row of the sector's n_dn
     uint32_t pad;
 };
 

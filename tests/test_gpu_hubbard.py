@@ -236,16 +236,11 @@ def test_lanczos_anderson_169_sectors_mixed():
 
 
 # --------------------------------------------------------------------------- launch shapes
-def test_every_launch_shape_gives_identical_products():
-    """Each row sums its terms in the same order whatever (k, G, block), so the
-    products are bitwise equal; the autotuner's choice is one of them."""
-    L = 14
-    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7), (6, 7)], U=[4.0] * L)
-    x = torch.from_numpy(2 * synth.uniform01(21, h.dim) - 1).cuda()
+def _shapes_equal(h, x, ks):
     ref = None
-    for k in (7, 14, 5):
-        for G in (1, 2, 4):
-            for block in (256, 512):
+    for k in ks:
+        for G in (0, 1, 2, 4):
+            for block in ((512,) if G == 0 else (256, 512)):
                 mbr.hubbard_set_config(h, k, G, block)
                 y = torch.empty_like(x)
                 mbr.hubbard_apply(h, x, y)
@@ -253,14 +248,48 @@ def test_every_launch_shape_gives_identical_products():
                     ref = y.clone()
                 else:
                     assert torch.equal(y, ref), (k, G, block)
+    return ref
+
+
+def test_every_launch_shape_gives_identical_products():
+    """Each row sums its terms in the same order and with the same fused
+    operations whatever (k, G, block), the alpha_dn-stationary kernel (G = 0)
+    included, so the products are bitwise equal; the autotuner's choice is
+    one of them."""
+    L = 14
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7), (6, 7)], U=[4.0] * L)
+    x = torch.from_numpy(2 * synth.uniform01(21, h.dim) - 1).cuda()
+    ref = _shapes_equal(h, x, (7, 14, 5))
     with pytest.raises(mbr.MbrError):
         mbr.hubbard_set_config(h, 7, 3, 512)
     cfg = mbr.hubbard_autotune(h, reps=2)
     say("autotuned", cfg)
-    assert cfg["tuned_ms"] > 0 and cfg["G"] in (1, 2, 4)
+    assert cfg["tuned_ms"] > 0 and cfg["G"] in (0, 1, 2, 4)
     y = torch.empty_like(x)
     mbr.hubbard_apply(h, x, y)
     assert torch.equal(y, ref)
+
+
+def test_launch_shapes_identical_small_sectors_and_bond_amplitudes():
+    """Small C_dn (several alpha_up blocks per rows-kernel tile, flattened rows
+    in the tile kernel), bond-dependent amplitudes and site energies: every
+    launch shape gives the same bits, and they match the oracle."""
+    L = 8
+    eps_b, V = synth.anderson_parameters(4, L - 1)
+    bonds = OH.star_bonds(V)
+    eps = [-1.5] + list(eps_b)
+    U = [3.0] + [0.0] * (L - 1)
+    sectors = [(4, 4), (3, 5), (2, 1), (5, 3), (0, 3)]
+    h = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps)
+    x = torch.from_numpy(2 * synth.uniform01(22, h.dim) - 1).cuda()
+    y = _shapes_equal(h, x, (4, 8, 3)).cpu().numpy()
+    tl = OH.terms(L, bonds, U, eps=eps)
+    off = 0
+    for nu, nd in sectors:
+        st = OH.sector(L, nu, nd)
+        want = OH.apply(st, tl, x.cpu().numpy()[off:off + st.size])
+        np.testing.assert_allclose(y[off:off + st.size], want, rtol=1e-13, atol=1e-13)
+        off += st.size
 
 
 def test_autotune_cache_roundtrip_and_corrupt_entries(tmp_path, monkeypatch):
