@@ -449,9 +449,9 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
 //    offset.
 //  * pipelining: the global loads of row slot r + 1 (up-hop rows, the list,
 //    the alpha_dn pattern and energy, the epilogue operand) are issued before
-//    the LDS work of slot r, and the next tile's x rows are copied straight
-//    into the other half of a double-buffered LDS tile while this one
-//    computes.
+//    the LDS work of slot r, and the next tile's x rows are loaded into
+//    registers while this one computes and stored to the other half of a
+//    double-buffered LDS tile at its end.
 // Tiles are visited in the XCD-binned order of the tile kernel.  Per row the
 // terms are summed in the same order and with the same fused operations as in
 // the tile kernel, so both give bitwise identical products.
@@ -625,45 +625,39 @@ __device__ __forceinline__ void rows_uplists(const HvArgs &a, const uint16_t *rt
     if (b == 0 && g < nblk) un[g] = (uint32_t)__popcll(bal & grp);
 }
 
-// Staging of a tile's x rows on the direct global-to-LDS path (no registers):
-// block g (C_dn rows) goes to byte g (C_dn + 1) sizeof(T) of the buffer in
-// 256-byte chunks, one wave instruction each.  Each wave then writes the
-// negated copy of its own chunks once its loads have landed, and the zero
-// after every block, so only the end-of-tile barrier is needed.
-typedef __attribute__((address_space(3))) void *lds_ptr_t;
+// Staging of a tile's x rows: each lane loads kRowsPre rows into registers
+// (a fixed number of loads, so the compiler's wait counts stay exact) while
+// the previous tile computes, then stores them at the end of that tile as x
+// at byte g (C_dn + 1) sizeof(T) + i sizeof(T) of the buffer for row
+// g C_dn + i, as -x at cs bytes further, and a zero after every block.
+constexpr int kRowsPre = (kRowsMaxX + kRowsBlock - 1) / kRowsBlock;
 
 template <class T>
-__device__ __forceinline__ void rows_stage_issue(const T *src, unsigned char *bb, uint32_t nblk, uint32_t cdn) {
-    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint32_t bytes = cdn * (uint32_t)sizeof(T);
-    const uint32_t nch = (bytes + 255) >> 8;
-    for (uint32_t j = w; j < nblk * nch; j += kRowsBlock / 64) {
-        const uint32_t g = j / nch, c = j - g * nch;
-        const uint32_t off = (c << 8) + l * 4;
-        if (off < bytes)
-            __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned char *>(src + (size_t)g * cdn) + off,
-                                             (lds_ptr_t)(bb + g * (bytes + (uint32_t)sizeof(T)) + (c << 8)), 4, 0,
-                                             0);
+__device__ __forceinline__ void rows_pre_load(const T *src, uint32_t rows, T (&pre)[kRowsPre]) {
+#pragma unroll
+    for (int j = 0; j < kRowsPre; ++j) {
+        const uint32_t e = threadIdx.x + j * kRowsBlock;
+        pre[j] = src[e < rows ? e : 0];
     }
 }
 
 template <class T>
-__device__ __forceinline__ void rows_stage_finish(unsigned char *bb, size_t cs, uint32_t nblk, uint32_t cdn) {
-    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint32_t bytes = cdn * (uint32_t)sizeof(T);
-    const uint32_t nch = (bytes + 255) >> 8;
-    // the sign is the top bit of each element: of every odd dword for fp64
-    const uint32_t flip = (sizeof(T) == 4 || (l & 1)) ? 0x80000000u : 0u;
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's chunks have landed
-    for (uint32_t j = w; j < nblk * nch; j += kRowsBlock / 64) {
-        const uint32_t g = j / nch, c = j - g * nch;
-        const uint32_t off = g * (bytes + (uint32_t)sizeof(T)) + (c << 8) + l * 4;
-        if ((c << 8) + l * 4 < bytes) {
-            const uint32_t v = *reinterpret_cast<const uint32_t *>(bb + off);
-            *reinterpret_cast<uint32_t *>(bb + cs + off) = v ^ flip;
+__device__ __forceinline__ void rows_pre_store(unsigned char *bb, size_t cs, uint32_t nblk, uint32_t cdn,
+                                               const T (&pre)[kRowsPre]) {
+    T *xp = reinterpret_cast<T *>(bb);
+    T *xm = reinterpret_cast<T *>(bb + cs);
+    const uint32_t rows = nblk * cdn;
+#pragma unroll
+    for (int j = 0; j < kRowsPre; ++j) {
+        const uint32_t e = threadIdx.x + j * kRowsBlock;
+        if (e < rows) {
+            const uint32_t g = e / cdn;
+            const uint32_t pos = e + g;  // g (C_dn + 1) + (e - g C_dn)
+            xp[pos] = pre[j];
+            xm[pos] = -pre[j];
         }
     }
-    if (threadIdx.x < nblk) reinterpret_cast<T *>(bb + threadIdx.x * (bytes + (uint32_t)sizeof(T)))[cdn] = (T)0;
+    if (threadIdx.x < nblk) xp[threadIdx.x * (cdn + 1) + cdn] = (T)0;
 }
 
 // Sum of the down-hop terms of one row: the list entries (byte offsets from
@@ -802,14 +796,15 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     {
         const RowsTile c = rows_desc_uniform(qc);
         unsigned char *bb = smem + LL.buf0;
-        rows_stage_issue<T>(x + c.base, bb, c.nblk, c.cdn);
+        T pre[kRowsPre];
+        rows_pre_load<T>(x + c.base, c.nblk * c.cdn, pre);
         const uint32_t au = ug < c.nblk ? a.hs_states[c.hs_up0 + ug] : 0u;
         const T eu = ug < c.nblk ? (T)a.hs_energy[c.hs_up0 + ug] : (T)0;
         act_c = a.ep.active ? a.ep.active[c.sector] : 1;
         c1_c = LZ ? (T)a.ep.c1[c.sector] : (T)1;
         c2_c = has_p ? (T)a.ep.c2[c.sector] : (T)0;
         rows_uplists<T>(a, rt, c.nblk, au, eu, bb, LL);
-        rows_stage_finish<T>(bb, LL.cs, c.nblk, c.cdn);
+        rows_pre_store<T>(bb, LL.cs, c.nblk, c.cdn, pre);
     }
     __syncthreads();
 
@@ -822,15 +817,16 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
         const bool active = __builtin_amdgcn_readfirstlane(act_c) != 0;
         const T c1 = uniform_val(c1_c), c2 = uniform_val(c2_c);
 
-        // the next tile's x rows go straight into the other buffer (free since
-        // the last barrier) while this tile computes; its scalars are loaded
+        // the next tile's x rows are loaded into registers while this tile
+        // computes, and so are its scalars
         unsigned char *nb2 = smem + LL.buf0 + (size_t)(buf ^ 1) * LL.bstride;
         RowsTile n{};
         uint32_t au_n = 0;
         T eu_n = 0;
+        T pre[kRowsPre];
         if (has_next) {
             n = rows_desc_uniform(qn);
-            rows_stage_issue<T>(x + n.base, nb2, n.nblk, n.cdn);
+            rows_pre_load<T>(x + n.base, n.nblk * n.cdn, pre);
             if (ug < n.nblk) {
                 au_n = a.hs_states[n.hs_up0 + ug];
                 eu_n = (T)a.hs_energy[n.hs_up0 + ug];
@@ -953,7 +949,7 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
         // next tile: up-hop targets, negated copy of the staged rows, zeros
         if (has_next) {
             rows_uplists<T>(a, rt, n.nblk, au_n, eu_n, nb2, LL);
-            rows_stage_finish<T>(nb2, LL.cs, n.nblk, n.cdn);
+            rows_pre_store<T>(nb2, LL.cs, n.nblk, n.cdn, pre);
         }
         __syncthreads();
         qc[0] = qn[0];
