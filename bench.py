@@ -1,6 +1,6 @@
 """Throughput of the ranking / H·x / Lanczos hot path on one MI355X.
 
-Workload (default): periodic Hubbard chain, L = 14 sites, t = 1, U = 4, sector
+Headline workload: periodic Hubbard chain, L = 14 sites, t = 1, U = 4, sector
 (N_up, N_dn) = (7, 7) with 3432^2 = 11,778,624 states, fp64 vectors, Lanczos
 from a seeded random unit start vector.  A step is one Lanczos step: the
 on-the-fly H·x (unrank both halves, staggered rank of every hop target,
@@ -9,7 +9,21 @@ partials, then alpha, w = u - alpha v_j, beta.  `value` is steps per second,
 i.e. full H·x products per second; `granks_per_s` counts the ranked hop
 targets.  All inputs are synthetic and resident in HBM before timing.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu]
+The other workloads of the path are measured after the headline and reported
+under "rows" (kernel time by HIP events on the launch stream, each result
+checked for exactness or against stored oracle energies):
+  staggered  sector M=24, N=12; 2^22 uniform member queries; k = 8
+  trie       M=32, N=16 with >= 6 of orbitals 0-7 occupied (66,110,671 states);
+             2^24 queries, 90% members and 10% non-members; k = 4 and 8
+  learned    learned index vs trie vs spin-product staggered rank on the
+             (7,7) chain sector as 28-bit patterns, and learned vs trie on
+             M = 32 with 8 + 8 particles (165,636,900 states); 2^24 queries
+  batched    Anderson impurity model (12 sites, U = 8, eps_d = -4), all 169
+             (N_up, N_dn) sectors, 150 steps with full reorthogonalisation:
+             batched graph-captured steps with fp32 vectors against per-sector
+             launches with fp64 vectors
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--rows all|none|a,b]
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is rejected.
 """
@@ -30,6 +44,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
+ROWS = ("staggered", "trie", "learned", "batched")
 
 
 def chain_bonds(L):
@@ -69,6 +84,169 @@ def cpu_baseline(budget_s: float):
                       f"scaled to whole products"}
 
 
+# --------------------------------------------------------------------------- helpers
+def time_launches(torch, fn, reps: int) -> float:
+    """Average milliseconds of fn() over reps back-to-back calls, by HIP events
+    recorded on torch's current stream, which is the stream the binding
+    launches on."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def hbm_roofline(bytes_per_launch: float, ms: float, kernel: str) -> dict:
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": kernel, "alg_bytes_per_launch": bytes_per_launch}
+
+
+def full_mask(M):
+    return (1 << M) - 1
+
+
+def member_queries(torch, mbr, sector, seed, n):
+    """n members drawn uniformly by index (SplitMix64 draw mod size) and their
+    indices, as device tensors (patterns via the sector's unrank table)."""
+    import synth
+    idx = torch.from_numpy(synth.uniform_indices(seed, n, sector.size).astype(np.int32)).cuda()
+    return mbr.unrank_batch(sector, idx), idx
+
+
+# --------------------------------------------------------------------------- rows
+def row_staggered(torch, mbr, reps):
+    """Staggered rank (Fig. fastrank), M = 24, N = 12, k = 8, 2^22 queries."""
+    M, N, k, nq = 24, 12, 8, 1 << 22
+    s = mbr.sector_build(M, [(full_mask(M), N, N)])
+    q, idx = member_queries(torch, mbr, s, 1, nq)
+    r = mbr.build_staggered_tables(M, N, k)
+    out = torch.empty(nq, dtype=torch.int32, device="cuda")
+    ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
+    exact = bool(torch.equal(out, idx))
+    return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
+            "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
+            "roofline": hbm_roofline(8.0 * nq, ms, "rank_staggered_kernel (4 B in, 4 B out per query)")}
+
+
+def row_trie(torch, mbr, reps):
+    """Trie rank + membership (Fig. trielookup, safe lookup of Sec. IV) on the
+    RAS-like sector M = 32, N = 16, >= 6 of orbitals 0-7 occupied."""
+    import synth
+    M, nq = 32, 1 << 24
+    nm = nq // 10
+    s = mbr.sector_build(M, [(full_mask(M), 16, 16), (0xFF, 6, 8)])
+    mem, idx = member_queries(torch, mbr, s, 3, nq - nm)
+    pool = synth.random_subset_patterns(33, nm + nm // 4, M, 16)
+    non = pool[np.bitwise_count(pool & np.uint64(0xFF)) <= 5][:nm]
+    assert non.size == nm
+    perm = torch.from_numpy(synth.shuffle_positions(34, nq)).cuda()
+    q = torch.cat([mem, torch.from_numpy(non.astype(np.uint32).view(np.int32)).cuda()])[perm].contiguous()
+    want = torch.cat([idx, torch.full((nm,), -1, dtype=torch.int32, device="cuda")])[perm]
+    out = torch.empty(nq, dtype=torch.int32, device="cuda")
+    res = {"workload": "M=32 N=16, >=6 of orbitals 0-7 occupied (66,110,671 states); 2^24 queries, "
+                       "90% members by uniform index, 10% non-members",
+           "n_states": s.size}
+    for k in (4, 8):
+        r = mbr.build_trie(s, k)
+        info = r.info()
+        ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
+        exact = bool(torch.equal(out, want))
+        # compulsory: query in, rank out; per member one entry of each level
+        # that does not fit LDS and one state-list word for the membership check
+        lvl = info.levels
+        res[f"k{k}"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
+                        "exact": exact, "levels": lvl, "trie_bytes": int(info.bytes),
+                        "overhead_f": info.bytes / 4 / s.size,
+                        "roofline": hbm_roofline(8.0 * nq, ms, "trie_rank_kernel (stream bytes only)")}
+        del r
+    return res
+
+
+def row_learned(torch, mbr, reps, big: bool):
+    """Learned index (network prediction, max-error window, exact search) against
+    the packed trie, and on the spin-product sector also against the
+    spin-resolved staggered rank, on 2^24 uniform member queries."""
+    out = {}
+    nq = 1 << 24
+    cases = [("chain_7x7_28bit", 28, [(0x3FFF, 7, 7), (0x3FFF << 14, 7, 7)], (14, 7, 7))]
+    if big:
+        cases.append(("m32_8x8", 32, [(0xFFFF, 8, 8), (0xFFFF0000, 8, 8)], None))
+    for name, M, cons, spin in cases:
+        s = mbr.sector_build(M, cons)
+        q, idx = member_queries(torch, mbr, s, 4, nq)
+        res = {"n_states": s.size}
+        trie = mbr.build_trie(s, 8)
+        t0 = time.perf_counter()
+        lr_ = mbr.learned_train(s, trie, epochs=8, batch=4096, lr=2e-3, seed=4,
+                                samples_per_epoch=min(s.size, 1 << 22), max_window=1 << 20)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        e, win = mbr.learned_max_error(lr_)
+        res["learned_train_s"] = train_s
+        res["learned_max_error"] = e
+        res["learned_uses_window"] = win
+        res["learned_train"] = "8 epochs x min(N_s, 2^22) samples, batch 4096, Adam lr 2e-3, seed 4"
+        rankers = [("trie_k8", trie), ("learned", lr_)]
+        if spin is not None:
+            rankers.append(("spin_staggered", mbr.build_spin_ranker(*spin, k=7)))
+        ranked = torch.empty(nq, dtype=torch.int32, device="cuda")
+        for rn, r in rankers:
+            ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=ranked), reps)
+            res[rn] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
+                       "exact": bool(torch.equal(ranked, idx))}
+        out[name] = res
+        del rankers, lr_, trie, s, q, idx
+    return out
+
+
+def row_batched(torch, mbr, steps: int):
+    """Anderson impurity model, all 169 sectors, `steps` Lanczos steps with full
+    reorthogonalisation: batched + graph + fp32 vectors against per-sector
+    launches with fp64 vectors.  Energies against the stored oracle values."""
+    import synth
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "anderson_12.json")))
+    Ls = 12
+    eps = [g["eps_d"]] + g["eps_bath"]
+    Us = [g["U"]] + [0.0] * (Ls - 1)
+    bonds = [(0, l + 1, -float(v)) for l, v in enumerate(g["V"])]  # +V (c+_0 c_l + h.c.)
+    sectors = [(nu, nd) for nu in range(Ls + 1) for nd in range(Ls + 1)]
+    res = {"workload": "Anderson impurity, 1 + 11 bath sites, U=8, eps_d=-4, all 169 sectors "
+                       f"(16,777,216 states), {steps} steps, full reorthogonalisation"}
+    for name, prec, batched in (("batched_graph_fp32", mbr.F32, True),
+                                ("per_sector_fp64", mbr.F64, False)):
+        h = mbr.hubbard_create(Ls, bonds, sectors, U=Us, eps=eps, precision=prec)
+        v0 = torch.from_numpy(synth.start_vector(5, h.dim)).cuda()
+        lz = mbr.lanczos_create(h, steps, reorth=True, batched=batched, use_graph=True)
+        mbr.lanczos_start(lz, v0)
+        mbr.lanczos_step(lz, 2)
+        mbr.lanczos_start(lz, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mbr.lanczos_step(lz, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e0, nst = mbr.lanczos_result(lz)
+        worst = max(abs(e0[i] - g["e0"][f"{nu},{nd}"]) / max(1.0, abs(g["e0"][f"{nu},{nd}"]))
+                    for i, (nu, nd) in enumerate(sectors))
+        x = torch.zeros(h.dim, dtype=torch.float32 if prec == mbr.F32 else torch.float64,
+                        device="cuda")
+        x.copy_(v0)
+        y = torch.empty_like(x)
+        hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 20)
+        res[name] = {"value": steps / dt, "unit": "Lanczos steps/s", "ms_per_step": dt * 1e3 / steps,
+                     "e0": float(e0.min()), "worst_rel_err_vs_oracle": worst,
+                     "hv_kernel_ms": hv_ms, "hv_per_s": 1e3 / hv_ms}
+        del lz, h
+        torch.cuda.synchronize()
+    return res
+
+
+# --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +255,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rows", default="all", help="extra workloads: all, none, or a comma list of "
+                                                  + ",".join(ROWS))
+    ap.add_argument("--no-big", action="store_true", help="skip the 165.6M-state learned-index sector")
     ap.add_argument("--k", type=int, default=0, help="half-pattern chunk width (0 = automatic)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--G", type=int, default=-1,
@@ -91,6 +272,10 @@ def main():
         print("bench.py runs on one GPU only: the path is built and measured on a single "
               "MI355X (see DESIGN.md for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    rows = [] if args.rows == "none" else (list(ROWS) if args.rows == "all" else args.rows.split(","))
+    for r in rows:
+        if r not in ROWS:
+            ap.error(f"unknown row {r!r}")
 
     import torch
     import paper_2203_04158_amd as mbr
@@ -137,21 +322,15 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     e0, nsteps = mbr.lanczos_result(lz)
+    del lz
 
     # dominant kernel: the H·x product, timed with HIP events on this stream
     x = v0.clone()
     y = torch.empty_like(x)
-    mbr.hubbard_apply(h, x, y)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.kernel_reps):
-        mbr.hubbard_apply(h, x, y)
-    ev1.record()
-    torch.cuda.synchronize()
-    hv_ms = ev0.elapsed_time(ev1) / args.kernel_reps
+    hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), args.kernel_reps)
     alg_bytes = 16.0 * dim  # x read once + y written once, fp64
-    achieved = alg_bytes / (hv_ms * 1e-3) / 1e9
+    roof = hbm_roofline(alg_bytes, hv_ms, "hv_rows_kernel (plain H·x)")
+    roof["traffic"] = None
 
     steps = args.steps
     ms_per_step = elapsed * 1e3 / steps
@@ -180,13 +359,33 @@ def main():
         "granks_per_s": value * hops / 1e9,
         "hops_per_product": hops,
         "hv_kernel_ms": hv_ms,
+        "hv_per_s": 1e3 / hv_ms,
         "e0": float(e0[0]),
         "e0_rel_err_vs_oracle": (abs(e0[0] - e_ref) / abs(e_ref)) if e_ref else None,
         "lanczos_steps_done": int(nsteps[0]),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "hv_kernel (plain H·x)", "alg_bytes_per_launch": alg_bytes},
+        "roofline": roof,
     }
+    del h, x, y
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    extra = {}
+    for r in rows:
+        t0 = time.perf_counter()
+        if r == "staggered":
+            extra[r] = row_staggered(torch, mbr, 50)
+        elif r == "trie":
+            extra[r] = row_trie(torch, mbr, 20)
+        elif r == "learned":
+            extra[r] = row_learned(torch, mbr, 20, big=not args.no_big)
+        elif r == "batched":
+            extra[r] = row_batched(torch, mbr, 150)
+        extra[r]["wall_s"] = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print(f"[bench] row {r} done in {extra[r]['wall_s']:.1f} s", file=sys.stderr, flush=True)
+    if extra:
+        out["rows"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
