@@ -83,7 +83,6 @@ struct StagArgs {
 };
 
 constexpr unsigned kBlock = 256;
-constexpr int kPerThread = 4;
 
 template <class P>
 __device__ __forceinline__ bool below_width(P x, int M) {
@@ -113,42 +112,92 @@ __device__ __forceinline__ void load_table(E *lds, const E *__restrict__ g, uint
     __syncthreads();
 }
 
+// V consecutive patterns (or ranks) moved by one 16-byte (V = 16 / sizeof(P))
+// or scalar (V = 1) access; the launcher picks V = 1 when a pointer is not
+// aligned to the vector.
+template <class P, int V>
+__device__ __forceinline__ void load_vec(const P *__restrict__ q, uint64_t j, P (&x)[V]) {
+    if constexpr (V == 1) {
+        x[0] = q[j];
+    } else {
+        typedef P vec_t __attribute__((ext_vector_type(V)));
+        const vec_t v = reinterpret_cast<const vec_t *>(q)[j];
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[i] = v[i];
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_vec(uint32_t *__restrict__ out, uint64_t j, const uint32_t (&r)[V]) {
+    if constexpr (V == 1) {
+        out[j] = r[0];
+    } else {
+        typedef uint32_t vec_t __attribute__((ext_vector_type(V)));
+        vec_t v;
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = r[i];
+        reinterpret_cast<vec_t *>(out)[j] = v;
+    }
+}
+
+// Rank of one query of a particle-number sector, MBR_NOT_FOUND outside it.
+template <class P, class E>
+__device__ __forceinline__ uint32_t stag_query(P x, const E *tab, const StagArgs &a) {
+    const int h = (sizeof(P) == 8) ? __popcll((uint64_t)x) : __popc((uint32_t)x);
+    const bool ok = below_width(x, a.M) && (a.N < 0 || h == a.N);
+    const uint64_t r = stag_rank<P, E>(ok ? x : (P)0, tab, a);  // 0 keeps every row in range
+    return ok ? (uint32_t)r : MBR_NOT_FOUND;
+}
+
+// Queries are handled as vectors of V patterns, kVecs vectors per lane and
+// batch (grid stride between a lane's vectors, so a wave's accesses stay
+// contiguous).  The first batch is loaded before the table is staged so that
+// its latency overlaps the staging; the n mod V last queries are ranked one
+// per lane at the end.
+constexpr int kVecs = 4;
+
 // USE_LDS = false reads the table through the caches instead (tables larger
 // than the LDS budget, e.g. k = 16 or 64-bit patterns with wide chunks).
-template <class P, class E, bool USE_LDS>
+template <class P, class E, bool USE_LDS, int V>
 __global__ void __launch_bounds__(kBlock) rank_staggered_kernel(const P *__restrict__ q, uint64_t n,
                                                                 uint32_t *__restrict__ out,
                                                                 const E *__restrict__ gtab,
                                                                 StagArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint64_t nv = n / V;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    P x[kVecs][V];
+    auto load = [&](uint64_t base) {
+#pragma unroll
+        for (int u = 0; u < kVecs; ++u) {
+            const uint64_t j = base + u * stride;
+            if (j < nv) load_vec<P, V>(q, j, x[u]);
+        }
+    };
+    load(t0);
     const E *tab = gtab;
     if constexpr (USE_LDS) {
         E *t = reinterpret_cast<E *>(lds_raw);
         load_table(t, gtab, a.nentries);
         tab = t;
     }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; base < n;
-         base += stride * kPerThread) {
-        P x[kPerThread];
-        bool ok[kPerThread];
+    for (uint64_t base = t0; base < nv; base += stride * kVecs) {
+        if (base != t0) load(base);
 #pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            uint64_t j = base + u * stride;
-            x[u] = (j < n) ? q[j] : (P)0;
-        }
+        for (int u = 0; u < kVecs; ++u) {
+            const uint64_t j = base + u * stride;
+            if (j < nv) {
+                uint32_t r[V];
 #pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            int h = (sizeof(P) == 8) ? __popcll((uint64_t)x[u]) : __popc((uint32_t)x[u]);
-            ok[u] = below_width(x[u], a.M) && (a.N < 0 || h == a.N);
-            if (!ok[u]) x[u] = 0;  // keeps every table row in range
+                for (int i = 0; i < V; ++i) r[i] = stag_query<P, E>(x[u][i], tab, a);
+                store_vec<V>(out, j, r);
+            }
         }
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            uint64_t j = base + u * stride;
-            uint64_t r = stag_rank<P, E>(x[u], tab, a);
-            if (j < n) out[j] = ok[u] ? (uint32_t)r : MBR_NOT_FOUND;
-        }
+    }
+    if (t0 < n - nv * V) {
+        const uint64_t j = nv * V + t0;
+        out[j] = stag_query<P, E>(q[j], tab, a);
     }
 }
 
@@ -158,30 +207,64 @@ struct SpinArgs {
     uint32_t mult;      // C(L, n_dn)
 };
 
-template <class P, class E, bool USE_LDS>
+// Eq. rankupdown: rank(alpha_up) C(L, n_dn) + rank(alpha_dn), spin-down in
+// the low L bits; MBR_NOT_FOUND outside the sector.
+template <class P, class E>
+__device__ __forceinline__ uint32_t spin_query(P x, const E *tab, const SpinArgs &a) {
+    const P hm = (P)((a.L >= 32 && sizeof(P) == 8) ? 0xFFFFFFFFull : ((1ull << a.L) - 1));
+    P dn = x & hm;
+    P up = (x >> a.L) & hm;
+    const int hd = (sizeof(P) == 8) ? __popcll((uint64_t)dn) : __popc((uint32_t)dn);
+    const int hu = (sizeof(P) == 8) ? __popcll((uint64_t)up) : __popc((uint32_t)up);
+    const bool ok = below_width(x, 2 * a.L) && hd == a.n_dn && hu == a.n_up;
+    if (!ok) {
+        dn = 0;
+        up = 0;
+    }
+    const uint64_t rd = stag_rank<P, E>(dn, tab, a.half);
+    const uint64_t ru = stag_rank<P, E>(up, tab, a.half);
+    return ok ? (uint32_t)(ru * a.mult + rd) : MBR_NOT_FOUND;
+}
+
+template <class P, class E, bool USE_LDS, int V>
 __global__ void __launch_bounds__(kBlock) rank_spin_kernel(const P *__restrict__ q, uint64_t n,
                                                            uint32_t *__restrict__ out,
                                                            const E *__restrict__ gtab, SpinArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint64_t nv = n / V;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    P x[kVecs][V];
+    auto load = [&](uint64_t base) {
+#pragma unroll
+        for (int u = 0; u < kVecs; ++u) {
+            const uint64_t j = base + u * stride;
+            if (j < nv) load_vec<P, V>(q, j, x[u]);
+        }
+    };
+    load(t0);
     const E *tab = gtab;
     if constexpr (USE_LDS) {
         E *t = reinterpret_cast<E *>(lds_raw);
         load_table(t, gtab, a.half.nentries);
         tab = t;
     }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const P hm = (P)((a.L >= 32 && sizeof(P) == 8) ? 0xFFFFFFFFull : ((1ull << a.L) - 1));
-    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
-        P x = q[j];
-        P dn = x & hm;
-        P up = (x >> a.L) & hm;
-        int hd = (sizeof(P) == 8) ? __popcll((uint64_t)dn) : __popc((uint32_t)dn);
-        int hu = (sizeof(P) == 8) ? __popcll((uint64_t)up) : __popc((uint32_t)up);
-        bool ok = below_width(x, 2 * a.L) && hd == a.n_dn && hu == a.n_up;
-        if (!ok) { dn = 0; up = 0; }
-        uint64_t rd = stag_rank<P, E>(dn, tab, a.half);
-        uint64_t ru = stag_rank<P, E>(up, tab, a.half);
-        out[j] = ok ? (uint32_t)(ru * a.mult + rd) : MBR_NOT_FOUND;
+    for (uint64_t base = t0; base < nv; base += stride * kVecs) {
+        if (base != t0) load(base);
+#pragma unroll
+        for (int u = 0; u < kVecs; ++u) {
+            const uint64_t j = base + u * stride;
+            if (j < nv) {
+                uint32_t r[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) r[i] = spin_query<P, E>(x[u][i], tab, a);
+                store_vec<V>(out, j, r);
+            }
+        }
+    }
+    if (t0 < n - nv * V) {
+        const uint64_t j = nv * V + t0;
+        out[j] = spin_query<P, E>(q[j], tab, a);
     }
 }
 
@@ -207,19 +290,57 @@ mbr_status set_lds(K kernel, size_t bytes) {
     return MBR_OK;
 }
 
-template <class P, class E>
-mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
-                       hipStream_t s) {
+// Vector width for a launch: 16-byte accesses when both the queries and the
+// ranks are aligned to them, otherwise one pattern per access.
+template <class P>
+bool vec_aligned(const void *q, const uint32_t *out) {
+    constexpr int V = 16 / sizeof(P);
+    return ((uintptr_t)q % 16 == 0) && ((uintptr_t)out % (4 * V) == 0);
+}
+
+template <class P, class E, int V>
+mbr_status launch_stag_v(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                         hipStream_t s) {
     StagArgs a = make_args(r->stag, r->N);
     size_t lds = a.nentries * sizeof(E);
-    unsigned grid = mbr::grid_for(n, kBlock * kPerThread, mbr::device_cu_count() * 4);
+    unsigned grid = mbr::grid_for((n + V - 1) / V, kBlock * kVecs, mbr::device_cu_count() * 8);
     if (lds <= kLdsTable) {
-        auto kern = rank_staggered_kernel<P, E, true>;
+        auto kern = rank_staggered_kernel<P, E, true, V>;
         MBR_TRY(set_lds(kern, lds));
         kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
     } else {
-        rank_staggered_kernel<P, E, false><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
-                                                                  r->stag.table.as<E>(), a);
+        rank_staggered_kernel<P, E, false, V><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
+                                                                     r->stag.table.as<E>(), a);
+    }
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+template <class P, class E>
+mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                       hipStream_t s) {
+    if (vec_aligned<P>(q, out)) return launch_stag_v<P, E, 16 / sizeof(P)>(r, q, n, out, s);
+    return launch_stag_v<P, E, 1>(r, q, n, out, s);
+}
+
+template <class P, class E, int V>
+mbr_status launch_spin_v(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                         hipStream_t s) {
+    SpinArgs a{};
+    a.half = make_args(r->stag, -1);
+    a.L = r->L;
+    a.n_up = r->n_up;
+    a.n_dn = r->n_dn;
+    a.mult = (uint32_t)mbr::binom(r->L, r->n_dn);
+    size_t lds = a.half.nentries * sizeof(E);
+    unsigned grid = mbr::grid_for((n + V - 1) / V, kBlock * kVecs, mbr::device_cu_count() * 8);
+    if (lds <= kLdsTable) {
+        auto kern = rank_spin_kernel<P, E, true, V>;
+        MBR_TRY(set_lds(kern, lds));
+        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
+    } else {
+        rank_spin_kernel<P, E, false, V><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
+                                                                r->stag.table.as<E>(), a);
     }
     MBR_HIP(hipGetLastError());
     return MBR_OK;
@@ -228,24 +349,8 @@ mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, uint32_t 
 template <class P, class E>
 mbr_status launch_spin(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                        hipStream_t s) {
-    SpinArgs a{};
-    a.half = make_args(r->stag, -1);
-    a.L = r->L;
-    a.n_up = r->n_up;
-    a.n_dn = r->n_dn;
-    a.mult = (uint32_t)mbr::binom(r->L, r->n_dn);
-    size_t lds = a.half.nentries * sizeof(E);
-    unsigned grid = mbr::grid_for(n, kBlock, mbr::device_cu_count() * 8);
-    if (lds <= kLdsTable) {
-        auto kern = rank_spin_kernel<P, E, true>;
-        MBR_TRY(set_lds(kern, lds));
-        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
-    } else {
-        rank_spin_kernel<P, E, false><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
-                                                             r->stag.table.as<E>(), a);
-    }
-    MBR_HIP(hipGetLastError());
-    return MBR_OK;
+    if (vec_aligned<P>(q, out)) return launch_spin_v<P, E, 16 / sizeof(P)>(r, q, n, out, s);
+    return launch_spin_v<P, E, 1>(r, q, n, out, s);
 }
 
 }  // namespace

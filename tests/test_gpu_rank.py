@@ -123,3 +123,36 @@ def test_spin_ranker(L, nu, nd, k):
     bad = synth.splitmix64(L * 31 + nu, 50000) & np.uint64((1 << min(32, 2 * L + 1)) - 1)
     got = host_rank(mbr.rank_batch(r, dev_u32(bad)))
     assert np.array_equal(got, OC.bisect_rank(st, bad))
+
+
+@pytest.mark.parametrize("kind", ["stag32", "stag64", "spin"])
+@pytest.mark.parametrize("qoff,ooff,n", [(0, 0, 1), (0, 0, 4097), (1, 0, 4099), (0, 3, 10001),
+                                         (2, 1, 70001), (0, 0, 0), (0, 0, 1 << 20)])
+def test_rank_ragged_and_unaligned(kind, qoff, ooff, n):
+    """Vector (16-byte) and scalar access paths: sizes with a ragged tail, and
+    query / output views that start off the vector alignment."""
+    import torch
+    if kind == "spin":
+        L, nu, nd = 12, 5, 6
+        st = OC.sector_enumerate(2 * L, OC.spin_constraints(L, nu, nd))
+        r = mbr.build_spin_ranker(L, nu, nd, 6)
+        lim, dev = (1 << (2 * L)) - 1, dev_u32
+    else:
+        M, N = (22, 9) if kind == "stag32" else (40, 4)
+        st = OC.sector_enumerate(M, OC.constraints(M, N)) if M <= 32 else None
+        r = mbr.build_staggered_tables(M, N, 7, width_bits=32 if M <= 32 else 64)
+        lim, dev = (1 << M) - 1, (dev_u32 if M <= 32 else dev_u64)
+    if st is not None:
+        idx = synth.uniform_indices(n + 5, n + qoff, st.size) if n + qoff else np.zeros(0, np.int64)
+        q = st[idx]
+        q[::7] = synth.splitmix64(n + 9, q[::7].size) & np.uint64(lim)  # non-members mixed in
+        want = OC.bisect_rank(st, q)
+    else:
+        q = synth.random_subset_patterns(n + 11, n + qoff, 40, 4) if n + qoff else np.zeros(0, np.uint64)
+        q[::5] = synth.splitmix64(n + 3, q[::5].size) & np.uint64(lim)
+        pc = np.array([bin(int(a)).count("1") for a in q], dtype=np.int64)
+        want = np.where(pc == 4, OC.cns_rank_batch(q).astype(np.int64), -1)
+    qd = dev(q)[qoff:]
+    out = torch.full((n + ooff,), 7, dtype=torch.int32, device="cuda")[ooff:]
+    mbr.rank_batch(r, qd, out=out)
+    assert np.array_equal(host_rank(out), want[qoff:])
