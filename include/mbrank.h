@@ -155,29 +155,44 @@ mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t 
  * k in 1..16.  The trie keeps a reference to `s`: destroy it before `s`. */
 mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
 
-/* Learned index (extension, not in the paper): a 32->64->64->1 ReLU network
- * with bf16 weights and fp32 accumulation predicts rank/size from the 32 bit
- * features; it is trained on the GPU on the sector's own list.  The largest
- * prediction error e over all members (measured with the query kernel itself)
- * bounds an exact bisection in states[p-e .. p+e]; sectors whose e exceeds
- * opts->max_window are ranked by `fallback` instead (the fallback must rank the
- * same sector; the learned ranker keeps a reference to it and to `s`).
- * width_bits must be 32. */
+/* Learned index (extension, not in the paper): a two-stage recursive model
+ * index.  Stage 1 is a 32->64->64->1 ReLU network with bf16 weights and fp32
+ * accumulation that predicts y ~ rank/size from the 32 bit features; it is
+ * trained on the GPU on the sector's own list (Adam, mean squared error).
+ * Stage 2 has n_leaves = 2^b leaves (about one per four members); leaf
+ * floor(y 2^b) records the smallest and largest rank of the members the
+ * network sends to it, measured with the query kernel's own arithmetic.  A
+ * query bisects states[lo..hi] of its leaf, so ranks are exact.  The recorded
+ * error e is the widest leaf window hi - lo; when it exceeds opts->max_window,
+ * `fallback` answers instead (the fallback must rank the same sector; the
+ * learned ranker keeps a reference to it and to `s`).  width_bits must be 32.
+ * Synchronises `stream`. */
 typedef struct {
     int32_t epochs;     /* passes over the sector list */
     int32_t batch;      /* samples per optimiser step (multiple of 256) */
-    float lr;           /* Adam step size */
+    float lr;           /* Adam step size (cosine decay over the run) */
     uint64_t seed;      /* weight initialisation and sample order */
-    uint64_t max_window;/* largest e still served by the window search */
+    uint64_t max_window;/* largest leaf window e still served by the window search */
     uint64_t samples_per_epoch; /* 0 = whole list */
 } mbr_learned_opts;
 
 mbr_status mbr_learned_train(const mbr_sector *s, const mbr_learned_opts *opts,
                              const mbr_ranker *fallback, mbr_ranker **out, void *stream);
 
-/* Recorded maximum prediction error e of a learned ranker, and whether it
- * answers through its own window search (1) or through the fallback (0). */
+/* Recorded error e of a learned ranker (widest leaf window, hi - lo), and
+ * whether it answers through its own window search (1) or the fallback (0). */
 mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses_window);
+
+typedef struct {
+    uint64_t n_leaves;            /* stage-2 leaves (a power of two) */
+    uint64_t max_window;          /* widest leaf window hi - lo (= e) */
+    double mean_window;           /* mean over members of their leaf's hi - lo + 1 */
+    uint64_t single_window_error; /* max |rint(size y) - rank| of stage 1 alone */
+    int32_t uses_window;
+} mbr_learned_info;
+
+/* Statistics of a learned ranker's two stages. */
+mbr_status mbr_learned_stats(const mbr_ranker *r, mbr_learned_info *info);
 
 /* Copy the learned ranker's parameters to host memory as fp32 in the order
  * W1[64][32], b1[64], W2[64][64], b2[64], w3[64], b3 (6337 values); these are

@@ -44,6 +44,11 @@ class LearnedOpts(C.Structure):
                 ("samples_per_epoch", C.c_uint64)]
 
 
+class LearnedInfo(C.Structure):
+    _fields_ = [("n_leaves", C.c_uint64), ("max_window", C.c_uint64), ("mean_window", C.c_double),
+                ("single_window_error", C.c_uint64), ("uses_window", C.c_int32)]
+
+
 class Bond(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("t", C.c_double)]
 
@@ -91,6 +96,7 @@ _SIGS = {
     "mbr_learned_max_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64),
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mbr_mlp_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -276,6 +282,14 @@ def learned_max_error(ranker: Ranker):
     w = C.c_int32()
     _check("mbr_learned_max_error", lib().mbr_learned_max_error(ranker.handle, C.byref(e), C.byref(w)))
     return int(e.value), bool(w.value)
+
+
+def learned_stats(ranker: Ranker) -> dict:
+    i = LearnedInfo()
+    _check("mbr_learned_stats", lib().mbr_learned_stats(ranker.handle, C.byref(i)))
+    return {"n_leaves": int(i.n_leaves), "max_window": int(i.max_window),
+            "mean_window": float(i.mean_window), "single_window_error": int(i.single_window_error),
+            "uses_window": bool(i.uses_window)}
 
 
 def learned_params(ranker: Ranker, stream=None) -> np.ndarray:

@@ -1,9 +1,17 @@
-// Learned index for ranking (an extension; the paper has none): a per-sector
-// network 32 bit features -> 64 -> 64 -> 1 (ReLU) predicts rank / N_s.  The
-// largest prediction error e over all members, measured with the query kernel
-// itself, bounds an exact bisection in states[p - e .. p + e], so answers are
-// exact: a member is always inside its window and a non-member is never found.
-// When e exceeds the caller's bound the fallback ranker answers instead.
+// Learned index for ranking (an extension; the paper has none), in two
+// stages as a recursive model index (Kraska et al., "The Case for Learned
+// Index Structures", 2018):
+//  * stage 1: a per-sector network 32 bit features -> 64 -> 64 -> 1 (ReLU)
+//    predicts y ~ rank / N_s;
+//  * stage 2: y selects one of n_leaves = 2^b leaves, leaf floor(y 2^b); each
+//    leaf records the smallest and largest rank of the members the network
+//    sends to it, measured with the query kernel's own arithmetic.
+// A query is answered by bisection in states[lo .. hi] of its leaf, so answers
+// are exact: a member always lies inside its leaf's window and a non-member is
+// never found.  The recorded error e is the widest leaf window (hi - lo); when
+// e exceeds the caller's bound the fallback ranker answers instead.  The
+// single-window error max |rint(N_s y) - i| of stage 1 alone is kept as a
+// statistic.
 //
 // Parameters (6337 fp32 masters): W1[64][32], b1[64], W2[64][64], b2[64],
 // w3[64], b3.  Queries use their bf16 roundings with fp32 accumulation.
@@ -187,11 +195,79 @@ __global__ void __launch_bounds__(256) mlp_maxerr_kernel(const uint16_t *__restr
     if ((threadIdx.x & 63) == 0) atomicMax(emax, e);
 }
 
+// Leaf of a network output: floor(y n_leaves) clamped to the leaves (n_leaves
+// is a power of two, so the product is exact in fp32); NaN and y <= 0 go to
+// leaf 0.
+__device__ __forceinline__ uint32_t leaf_of(float y, uint32_t nleaf) {
+    if (!(y > 0.f)) return 0u;
+    if (y >= 1.f) return nleaf - 1u;
+    return (uint32_t)(y * (float)nleaf);
+}
+
+// Empty leaves: lo = all ones, hi = 0 (an empty window).
+__global__ void leaf_clear_kernel(uint2 *leaf, uint32_t nleaf) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nleaf) leaf[i] = make_uint2(0xFFFFFFFFu, 0u);
+}
+
+// Stage-2 windows: every member i widens the window of its leaf to include i.
+__global__ void __launch_bounds__(256) leaf_build_kernel(const uint16_t *__restrict__ wb,
+                                                         const uint32_t *__restrict__ states, uint64_t n,
+                                                         uint32_t nleaf, uint2 *__restrict__ leaf) {
+    MlpFrags f;
+    load_frags(f, wb);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + (threadIdx.x & 63);
+        const uint32_t a = i < n ? states[i] : 0u;
+        const float y = mlp64(f, a);
+        if (i < n) {
+            uint32_t *w = reinterpret_cast<uint32_t *>(leaf + leaf_of(y, nleaf));
+            atomicMin(w, (uint32_t)i);
+            atomicMax(w + 1, (uint32_t)i);
+        }
+    }
+}
+
+// Window statistics over the members: acc[0] += hi - lo + 1 of each member's
+// leaf (the mean window is acc[0] / n), acc[1] = max (hi - lo).
+__global__ void __launch_bounds__(256) leaf_stats_kernel(const uint16_t *__restrict__ wb,
+                                                         const uint32_t *__restrict__ states, uint64_t n,
+                                                         uint32_t nleaf, const uint2 *__restrict__ leaf,
+                                                         unsigned long long *acc) {
+    MlpFrags f;
+    load_frags(f, wb);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long sum = 0, mx = 0;
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + (threadIdx.x & 63);
+        const uint32_t a = i < n ? states[i] : 0u;
+        const float y = mlp64(f, a);
+        if (i < n) {
+            const uint2 w = leaf[leaf_of(y, nleaf)];
+            const unsigned long long d = (unsigned long long)(w.y - w.x);
+            sum += d + 1;
+            mx = d > mx ? d : mx;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_down(sum, o, 64);
+        const unsigned long long v = __shfl_down(mx, o, 64);
+        mx = v > mx ? v : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(acc, sum);
+        atomicMax(acc + 1, mx);
+    }
+}
+
 __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__restrict__ wb,
                                                            const uint32_t *__restrict__ states,
-                                                           uint64_t n, uint64_t e, int M,
-                                                           const uint32_t *__restrict__ q, uint64_t nq,
-                                                           uint32_t *__restrict__ out) {
+                                                           const uint2 *__restrict__ leaf, uint32_t nleaf,
+                                                           int M, const uint32_t *__restrict__ q,
+                                                           uint64_t nq, uint32_t *__restrict__ out) {
     MlpFrags f;
     load_frags(f, wb);
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -199,22 +275,22 @@ __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__res
          base += waves * 64) {
         const uint64_t j = base + (threadIdx.x & 63);
         const uint32_t a = j < nq ? q[j] : 0u;
-        const float y = mlp64(f, a);
+        const float y = mlp64(f, a);  // every lane of the wave takes part
         if (j >= nq) continue;
         const bool in_width = M >= 32 || (a >> M) == 0;
-        const int64_t p = predict_rank(y, n);
-        uint64_t lo = p > (int64_t)e ? (uint64_t)(p - (int64_t)e) : 0;
-        uint64_t hi = (uint64_t)p + e;
-        if (hi > n - 1) hi = n - 1;
-        // lower bound of a in states[lo .. hi]
-        uint64_t L = lo, R = hi + 1;
-        while (L < R) {
-            const uint64_t mid = (L + R) >> 1;
-            if (states[mid] < a) L = mid + 1;
-            else R = mid;
+        const uint2 w = leaf[leaf_of(y, nleaf)];
+        // lower bound of a in states[lo .. hi] (empty when lo > hi)
+        uint32_t L = w.x, R = w.y + 1u;
+        bool hit = false;
+        if (in_width && w.x <= w.y) {
+            while (L < R) {
+                const uint32_t mid = L + ((R - L) >> 1);
+                if (states[mid] < a) L = mid + 1;
+                else R = mid;
+            }
+            hit = L <= w.y && states[L] == a;
         }
-        const bool hit = in_width && L <= hi && states[L] == a;
-        out[j] = hit ? (uint32_t)L : MBR_NOT_FOUND;
+        out[j] = hit ? L : MBR_NOT_FOUND;
     }
 }
 
@@ -453,13 +529,17 @@ struct LearnedModel {
     uint64_t n = 0;
     int32_t M = 0;
     mbr::DevBuf w, m, v, wr, wb;  // masters, Adam moments, rounded fp32, bf16
-    uint64_t e = 0;
+    mbr::DevBuf leaf;             // stage-2 windows, uint2 {lo, hi} per leaf
+    uint32_t n_leaves = 0;
+    uint64_t e = 0;               // widest leaf window, hi - lo
+    uint64_t e_single = 0;        // max |rint(N_s y) - i| of stage 1 alone
+    double mean_window = 0;       // member-weighted mean of hi - lo + 1
     int32_t uses_window = 0;
     double last_loss = 0;
 };
 
 void learned_free(LearnedModel *m) { delete m; }
-uint64_t learned_bytes(const LearnedModel *m) { return m ? (uint64_t)kParams * 2 : 0; }
+uint64_t learned_bytes(const LearnedModel *m) { return m ? (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8 : 0; }
 
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                hipStream_t s) {
@@ -470,7 +550,8 @@ mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, u
     }
     const unsigned grid = mbr::grid_for(n, 256, mbr::device_cu_count() * 8);
     learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(),
-                                             lm.n, lm.e, lm.M, static_cast<const uint32_t *>(q), n, out);
+                                             lm.leaf.as<uint2>(), lm.n_leaves, lm.M,
+                                             static_cast<const uint32_t *>(q), n, out);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
@@ -552,13 +633,31 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
     mlp_maxerr_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
                                            d_e.as<unsigned long long>());
     MBR_HIP(hipGetLastError());
-    unsigned long long e = 0;
+    // stage 2: leaf windows (about four members per leaf), then their statistics
+    uint64_t nl = 256;
+    while (nl < sec->n / 4 && nl < (1ull << 26)) nl <<= 1;
+    lm->n_leaves = (uint32_t)nl;
+    MBR_TRY(lm->leaf.alloc(nl * 8));
+    leaf_clear_kernel<<<(unsigned)((nl + 255) / 256), 256, 0, s>>>(lm->leaf.as<uint2>(), (uint32_t)nl);
+    leaf_build_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
+                                           (uint32_t)nl, lm->leaf.as<uint2>());
+    DevBuf d_acc;
+    MBR_TRY(d_acc.alloc(16));
+    MBR_HIP(hipMemsetAsync(d_acc.p, 0, 16, s));
+    leaf_stats_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
+                                           (uint32_t)nl, lm->leaf.as<uint2>(), d_acc.as<unsigned long long>());
+    MBR_HIP(hipGetLastError());
+    unsigned long long e = 0, acc[2] = {0, 0};
     MBR_HIP(hipMemcpyAsync(&e, d_e.p, 8, hipMemcpyDeviceToHost, s));
+    MBR_HIP(hipMemcpyAsync(acc, d_acc.p, 16, hipMemcpyDeviceToHost, s));
     MBR_HIP(hipStreamSynchronize(s));
-    lm->e = e;
-    lm->uses_window = (e <= o->max_window) ? 1 : 0;
+    lm->e_single = e;
+    lm->e = acc[1];
+    lm->mean_window = (double)acc[0] / (double)sec->n;
+    lm->uses_window = (lm->e <= o->max_window) ? 1 : 0;
     if (!lm->uses_window && !fallback)
-        MBR_FAIL(MBR_ERANGE, "max error %llu exceeds max_window and no fallback was given", e);
+        MBR_FAIL(MBR_ERANGE, "widest leaf window %llu exceeds max_window and no fallback was given",
+                 (unsigned long long)lm->e);
     auto *r = new (std::nothrow) mbr_ranker;
     if (!r) MBR_FAIL(MBR_ENOMEM, "host allocation");
     r->kind = MBR_RANKER_LEARNED;
@@ -578,6 +677,17 @@ mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses
     if (!r || r->kind != MBR_RANKER_LEARNED) MBR_FAIL(MBR_EINVAL, "not a learned ranker");
     if (e) *e = r->learned->e;
     if (uses_window) *uses_window = r->learned->uses_window;
+    return MBR_OK;
+}
+
+mbr_status mbr_learned_stats(const mbr_ranker *r, mbr_learned_info *info) {
+    if (!r || r->kind != MBR_RANKER_LEARNED || !info) MBR_FAIL(MBR_EINVAL, "not a learned ranker");
+    const LearnedModel &lm = *r->learned;
+    info->n_leaves = lm.n_leaves;
+    info->max_window = lm.e;
+    info->mean_window = lm.mean_window;
+    info->single_window_error = lm.e_single;
+    info->uses_window = lm.uses_window;
     return MBR_OK;
 }
 

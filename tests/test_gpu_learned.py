@@ -90,34 +90,59 @@ def _learned(M, cons, epochs, batch=4096, lr=3e-3, max_window=1 << 20, k=8, seed
     return s, trie, lr_
 
 
+def _leaf_windows(y, nleaf, n):
+    """Stage-2 windows recomputed on the host from the network outputs y of the
+    members 0..n-1 (same leaf rule as the library: floor(y nleaf) in fp32,
+    clamped, NaN and y <= 0 to leaf 0)."""
+    yf = np.asarray(y, dtype=np.float32)
+    with np.errstate(invalid="ignore"):
+        b = np.where(~(yf > 0), 0, np.where(yf >= 1, nleaf - 1,
+                     np.floor(yf * np.float32(nleaf)))).astype(np.int64)
+    lo = np.full(nleaf, np.iinfo(np.int64).max)
+    hi = np.full(nleaf, -1)
+    np.minimum.at(lo, b, np.arange(n))
+    np.maximum.at(hi, b, np.arange(n))
+    return b, lo, hi
+
+
 def test_learned_ranks_exact_and_error_recorded():
     M, cons = 20, OC.constraints(20, 10)
     st = OC.sector_enumerate(M, cons)
     s, trie, lr_ = _learned(M, cons, epochs=30)
     e, win = mbr.learned_max_error(lr_)
-    assert win
+    info = mbr.learned_stats(lr_)
+    assert win and info["uses_window"] and info["max_window"] == e
     got = host_rank(mbr.rank_batch(lr_, dev_u32(st)))
     assert np.array_equal(got, np.arange(st.size))
     noise = synth.splitmix64(77, 50000) & np.uint64((1 << 21) - 1)
     got = host_rank(mbr.rank_batch(lr_, dev_u32(noise)))
     assert np.array_equal(got, OC.bisect_rank(st, noise))
-    # the recorded e is the true maximum error of the query-time network
+    # the recorded windows are those of the query-time network
     params = torch.from_numpy(mbr.learned_params(lr_)).cuda()
     y = mbr.mlp_forward(params, dev_u32(np.concatenate([st, np.zeros((-st.size) % 64, np.uint64)])))
-    y = y.cpu().numpy().astype(np.float64)[: st.size]
-    p = np.clip(np.rint(st.size * y), 0, st.size - 1)
-    assert int(np.abs(p - np.arange(st.size)).max()) == e
-    say("learned M=20 N=10 e", e, "of", st.size)
+    y = y.cpu().numpy()[: st.size]
+    nl = info["n_leaves"]
+    assert nl >= st.size // 4 and nl & (nl - 1) == 0
+    b, lo, hi = _leaf_windows(y, nl, st.size)
+    assert int((hi - lo)[hi >= 0].max()) == e
+    assert abs(info["mean_window"] - float((hi[b] - lo[b] + 1).mean())) <= 1e-9 * info["mean_window"]
+    p = np.clip(np.rint(st.size * y.astype(np.float64)), 0, st.size - 1)
+    assert int(np.abs(p - np.arange(st.size)).max()) == info["single_window_error"]
+    say("learned M=20 N=10: leaf windows max", e, "mean", info["mean_window"],
+        "single-window error", info["single_window_error"], "of", st.size)
 
 
 def test_training_gain_over_untrained_network():
+    """What training buys: the stage-2 windows of the untrained network are
+    far wider than those of the trained one, and so is stage 1's own error."""
     M, cons = 20, OC.constraints(20, 10)
     _, _, untrained = _learned(M, cons, epochs=0)
     _, _, trained = _learned(M, cons, epochs=30)
-    e0, _ = mbr.learned_max_error(untrained)
-    e1, _ = mbr.learned_max_error(trained)
-    say("untrained e", e0, "trained e", e1)
-    assert e1 * 10 < e0
+    u, t = mbr.learned_stats(untrained), mbr.learned_stats(trained)
+    say("untrained", u, "trained", t)
+    assert t["mean_window"] * 10 < u["mean_window"]
+    assert t["max_window"] * 10 < u["max_window"]
+    assert t["single_window_error"] * 10 < u["single_window_error"]
 
 
 def test_single_particle_sector_learns_exactly():
@@ -148,3 +173,25 @@ def test_training_is_repeatable():
     _, _, b = _learned(M, cons, epochs=5, seed=9)
     assert np.array_equal(mbr.learned_params(a), mbr.learned_params(b))
     assert mbr.learned_max_error(a) == mbr.learned_max_error(b)
+
+
+def test_learned_chain_sector_full_size():
+    """The (7,7) chain sector as 28-bit patterns (11,778,624 states), trained
+    as in the ranking benchmark, with the window search forced (max_window
+    above any leaf window): every member ranks to its index and seeded
+    arbitrary 28-bit patterns agree with bisection on the oracle's list."""
+    M, cons = 28, OC.spin_constraints(14, 7, 7)
+    s = mbr.sector_build(M, cons)
+    trie = mbr.build_trie(s, 8)
+    lr_ = mbr.learned_train(s, trie, epochs=8, batch=4096, lr=2e-3, seed=4,
+                            samples_per_epoch=1 << 22, max_window=1 << 30)
+    info = mbr.learned_stats(lr_)
+    say("chain sector learned", info)
+    assert info["uses_window"] and info["max_window"] < s.size
+    idx = torch.arange(s.size, dtype=torch.int32, device="cuda")
+    got = mbr.rank_batch(lr_, s.states())
+    assert torch.equal(got, idx)
+    st = OC.sector_enumerate(M, cons)
+    noise = synth.splitmix64(78, 1 << 20) & np.uint64((1 << 28) - 1)
+    q = np.concatenate([noise, st[synth.uniform_indices(79, 1 << 20, st.size)]])
+    assert np.array_equal(host_rank(mbr.rank_batch(lr_, dev_u32(q))), OC.bisect_rank(st, q))
