@@ -106,6 +106,33 @@ def hbm_roofline(bytes_per_launch: float, ms: float, kernel: str) -> dict:
             "frac": achieved / HBM_PEAK_GBS, "kernel": kernel, "alg_bytes_per_launch": bytes_per_launch}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hv_rows_and_rank.md")
+L2_BYTES = 4 << 20       # L2 of one XCD
+GRANULE = 64             # bytes of the smallest HBM access a random gather costs
+
+
+def traffic_for(key: str):
+    """HBM bytes per launch of kernel `key` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record in profiles/ (scaled by the plain-copy calibration stored
+    with it), or None when there is no record or the kernel's source file has
+    changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("traffic-record "):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split()[1:])
+        if f.get("kernel") != key:
+            continue
+        src = os.path.join(ROOT, f["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
+            return None
+        return (float(f["fetch_kib"]) * float(f["fetch_scale"])
+                + float(f["write_kib"]) * float(f["write_scale"])) * 1024.0
+    return None
+
+
 def full_mask(M):
     return (1 << M) - 1
 
@@ -128,9 +155,11 @@ def row_staggered(torch, mbr, reps):
     out = torch.empty(nq, dtype=torch.int32, device="cuda")
     ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
     exact = bool(torch.equal(out, idx))
+    roof = hbm_roofline(8.0 * nq, ms, "rank_staggered_kernel (4 B in, 4 B out per query)")
+    roof["traffic"] = traffic_for("rank_staggered_kernel<unsignedint,unsignedint,true,4>")
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
-            "roofline": hbm_roofline(8.0 * nq, ms, "rank_staggered_kernel (4 B in, 4 B out per query)")}
+            "roofline": roof}
 
 
 def row_trie(torch, mbr, reps):
@@ -156,13 +185,21 @@ def row_trie(torch, mbr, reps):
         info = r.info()
         ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
         exact = bool(torch.equal(out, want))
-        # compulsory: query in, rank out; per member one entry of each level
-        # that does not fit LDS and one state-list word for the membership check
-        lvl = info.levels
+        # algorithmic bytes per query: the query in and the rank out, plus one
+        # HBM granule for every dependent gather into an array that neither LDS
+        # nor an XCD's L2 holds (levels below the staged ones, and the state
+        # list of the membership check)
+        ent, lds_lv = mbr.trie_level_entries(r)
+        far = [l for l in range(len(ent)) if l >= lds_lv and 4 * ent[l] > L2_BYTES]
+        gathers = len(far) + (1 if 4 * s.size > L2_BYTES else 0)
+        per_q = 8.0 + GRANULE * gathers
+        roof = hbm_roofline(per_q * nq, ms, f"trie_rank_kernel ({per_q:.0f} B per query: 8 B stream + "
+                                            f"{gathers} random {GRANULE}-B granules)")
+        roof["traffic"] = traffic_for(f"trie_rank_kernel<unsignedint>@k{k}")
         res[f"k{k}"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
-                        "exact": exact, "levels": lvl, "trie_bytes": int(info.bytes),
-                        "overhead_f": info.bytes / 4 / s.size,
-                        "roofline": hbm_roofline(8.0 * nq, ms, "trie_rank_kernel (stream bytes only)")}
+                        "exact": exact, "levels": info.levels, "lds_levels": lds_lv,
+                        "level_bytes": [4 * e for e in ent], "trie_bytes": int(info.bytes),
+                        "overhead_f": info.bytes / 4 / s.size, "roofline": roof}
         del r
     return res
 
@@ -239,11 +276,15 @@ def row_batched(torch, mbr, steps: int):
         x.copy_(v0)
         y = torch.empty_like(x)
         hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 20)
+        tsz = 4 if prec == mbr.F32 else 8
         res[name] = {"value": steps / dt, "unit": "Lanczos steps/s", "ms_per_step": dt * 1e3 / steps,
                      "e0": float(e0.min()), "worst_rel_err_vs_oracle": worst,
-                     "hv_kernel_ms": hv_ms, "hv_per_s": 1e3 / hv_ms}
+                     "hv_kernel_ms": hv_ms, "hv_per_s": 1e3 / hv_ms,
+                     "hv_roofline": hbm_roofline(2.0 * tsz * h.dim, hv_ms,
+                                                 f"H·x over all 169 sectors ({2 * tsz} B per row)")}
         del lz, h
         torch.cuda.synchronize()
+    res["speedup_steps"] = res["batched_graph_fp32"]["value"] / res["per_sector_fp64"]["value"]
     return res
 
 
@@ -331,7 +372,7 @@ def main():
     hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), args.kernel_reps)
     alg_bytes = 16.0 * dim  # x read once + y written once, fp64
     roof = hbm_roofline(alg_bytes, hv_ms, "hv_rows_kernel (plain H·x)")
-    roof["traffic"] = None
+    roof["traffic"] = traffic_for("hv_rows_kernel<double,false,4,true>") if launch_cfg["G"] == 0 else None
 
     steps = args.steps
     ms_per_step = elapsed * 1e3 / steps

@@ -155,6 +155,12 @@ mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t 
  * k in 1..16.  The trie keeps a reference to `s`: destroy it before `s`. */
 mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
 
+/* Layout of a trie ranker: *levels = number of levels (chunks), *lds_levels =
+ * how many top levels each workgroup stages in LDS, entries[l] = uint32
+ * entries of level l (padding included) for l < min(levels, cap). */
+mbr_status mbr_trie_level_entries(const mbr_ranker *r, uint64_t *entries, int32_t cap,
+                                  int32_t *levels, int32_t *lds_levels);
+
 /* Learned index (extension, not in the paper): a two-stage recursive model
  * index.  Stage 1 is a 32->64->64->1 ReLU network with bf16 weights and fp32
  * accumulation that predicts y ~ rank/size from the 32 bit features; it is

@@ -97,6 +97,8 @@ _SIGS = {
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mbr_trie_level_entries": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32)]),
     "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mbr_mlp_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -265,6 +267,15 @@ def build_trie(sector: Sector, k: int, stream=None) -> Ranker:
     h = C.c_void_p()
     _check("mbr_build_trie", lib().mbr_build_trie(sector.handle, k, C.byref(h), _stream(stream)))
     return Ranker(h, keep=(sector,))
+
+
+def trie_level_entries(ranker: Ranker):
+    """(entries per level, number of top levels staged in LDS) of a trie ranker."""
+    out = np.zeros(64, dtype=np.uint64)
+    lv, ld = C.c_int32(), C.c_int32()
+    _check("mbr_trie_level_entries", lib().mbr_trie_level_entries(
+        ranker.handle, C.c_void_p(out.ctypes.data), 64, C.byref(lv), C.byref(ld)))
+    return [int(v) for v in out[: lv.value]], int(ld.value)
 
 
 def learned_train(sector: Sector, fallback: Ranker, epochs: int = 4, batch: int = 4096,

@@ -253,6 +253,17 @@ mbr_status rank_trie_launch(const mbr_ranker *r, const void *q, uint64_t n, uint
     return launch_trie<uint64_t>(r, q, n, out, s);
 }
 
+extern "C" mbr_status mbr_trie_level_entries(const mbr_ranker *r, uint64_t *entries, int32_t cap,
+                                             int32_t *levels, int32_t *lds_levels) {
+    if (!r || r->kind != MBR_RANKER_TRIE || !r->trie) MBR_FAIL(MBR_EINVAL, "not a trie ranker");
+    const TrieLevels &t = *r->trie;
+    if (levels) *levels = t.H;
+    if (lds_levels) *lds_levels = (int32_t)t.lds_levels;
+    if (entries)
+        for (int l = 0; l < t.H && l < cap; ++l) entries[l] = t.off[l + 1] - t.off[l];
+    return MBR_OK;
+}
+
 extern "C" mbr_status mbr_build_trie(const mbr_sector *sec, int32_t k, mbr_ranker **out,
                                      void *stream) {
     using namespace mbr;

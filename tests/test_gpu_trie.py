@@ -31,6 +31,9 @@ def _check(M, cons, k, width=32, n_noise=20000, seed=1):
     r = mbr.build_trie(s, k)
     info = r.info()
     assert info.levels == -(-M // k)
+    ent, lds_lv = mbr.trie_level_entries(r)
+    assert len(ent) == info.levels and 4 * sum(ent) == info.bytes and 0 <= lds_lv <= info.levels
+    assert ent[0] == 1 << OT.chunk_widths(M, k, "last")[0]  # the root is a full node
     if M - OT.chunk_widths(M, k, "last")[-1] <= 26:  # range of the oracle's size counter
         assert info.bytes == 4 * _expected_entries(st, M, k)
     dev = dev_u32 if width == 32 else dev_u64
