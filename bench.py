@@ -22,6 +22,9 @@ checked for exactness or against stored oracle energies):
              (N_up, N_dn) sectors, 150 steps with full reorthogonalisation:
              batched graph-captured steps with fp32 vectors against per-sector
              launches with fp64 vectors
+  sweep      (by name only) the ranking microbenchmark of Sec. V.A: M = 28,
+             N = 1..27, sorted queries, bisection / combinadics / staggered /
+             trie at R = 4, 8, 12
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--rows all|none|a,b]
 
@@ -45,6 +48,7 @@ METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
 ROWS = ("staggered", "trie", "learned", "batched")
+EXTRA_ROWS = ("sweep",)   # run only when asked for by name
 
 
 def chain_bonds(L):
@@ -242,6 +246,47 @@ def row_learned(torch, mbr, reps, big: bool):
     return out
 
 
+def row_sweep(torch, mbr, reps):
+    """The ranking microbenchmark of Sec. V.A on the GPU: M = 28 orbitals and
+    every sector N = 1..27; 2^22 queries per sector drawn uniformly with
+    replacement and ordered by value (as the paper does); bisection,
+    combinadics ranking (Fig. algr), staggered lookup and trie lookup at
+    R = 4, 8, 12.  Kernel time per lookup, exactness, and the trie's memory
+    overhead f = trie bytes / (4 N_s)."""
+    import synth
+    M, nq = 28, 1 << 22
+    ranked = torch.empty(nq, dtype=torch.int32, device="cuda")
+    methods = ["bisect", "cns"] + [f"staggered_k{k}" for k in (4, 8, 12)] + [f"trie_k{k}" for k in (4, 8, 12)]
+    ns = {m: [] for m in methods}
+    f = {f"trie_k{k}": [] for k in (4, 8, 12)}
+    exact = True
+    sizes = []
+    for N in range(1, M):
+        s = mbr.sector_build(M, [(full_mask(M), N, N)])
+        sizes.append(s.size)
+        idx = torch.from_numpy(np.sort(synth.uniform_indices(100 + N, nq, s.size)).astype(np.int32)).cuda()
+        q = mbr.unrank_batch(s, idx)
+        for m in methods:
+            if m == "bisect":
+                r = mbr.build_bisect_ranker(s)
+            elif m == "cns":
+                r = mbr.build_cns_ranker(M, N)
+            elif m.startswith("staggered"):
+                r = mbr.build_staggered_tables(M, N, int(m.split("_k")[1]))
+            else:
+                r = mbr.build_trie(s, int(m.split("_k")[1]))
+                f[m].append(r.info().bytes / 4 / s.size)
+            ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=ranked), reps)
+            exact = exact and bool(torch.equal(ranked, idx))
+            ns[m].append(ms * 1e6 / nq)
+            del r
+        del s, q, idx
+        print(f"[bench] sweep N={N} done", file=sys.stderr, flush=True)
+    return {"workload": "M=28, N=1..27, 2^22 sorted uniform queries per sector",
+            "n_states": sizes, "ns_per_lookup": ns, "trie_overhead_f": f, "exact": exact,
+            "half_filled_granks_per_s": {m: 1.0 / ns[m][13] for m in methods}}
+
+
 def row_batched(torch, mbr, steps: int):
     """Anderson impurity model, all 169 sectors, `steps` Lanczos steps with full
     reorthogonalisation: batched + graph + fp32 vectors against per-sector
@@ -297,8 +342,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--rows", default="all", help="extra workloads: all, none, or a comma list of "
-                                                  + ",".join(ROWS))
+    ap.add_argument("--rows", default="all", help="extra workloads: all (" + ",".join(ROWS) + "), none, "
+                                                  "or a comma list that may also name " + ",".join(EXTRA_ROWS))
     ap.add_argument("--no-big", action="store_true", help="skip the 165.6M-state learned-index sector")
     ap.add_argument("--k", type=int, default=0, help="half-pattern chunk width (0 = automatic)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
@@ -316,7 +361,7 @@ def main():
         sys.exit(2)
     rows = [] if args.rows == "none" else (list(ROWS) if args.rows == "all" else args.rows.split(","))
     for r in rows:
-        if r not in ROWS:
+        if r not in ROWS + EXTRA_ROWS:
             ap.error(f"unknown row {r!r}")
 
     import torch
@@ -422,6 +467,8 @@ def main():
             extra[r] = row_learned(torch, mbr, 20, big=not args.no_big)
         elif r == "batched":
             extra[r] = row_batched(torch, mbr, 150)
+        elif r == "sweep":
+            extra[r] = row_sweep(torch, mbr, 10)
         extra[r]["wall_s"] = time.perf_counter() - t0
         torch.cuda.synchronize()
         torch.cuda.empty_cache()

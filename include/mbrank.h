@@ -109,6 +109,8 @@ typedef struct mbr_ranker mbr_ranker;
 #define MBR_RANKER_SPIN      2
 #define MBR_RANKER_TRIE      3
 #define MBR_RANKER_LEARNED   4
+#define MBR_RANKER_BISECT    5
+#define MBR_RANKER_CNS       6
 
 typedef struct {
     int32_t kind;       /* MBR_RANKER_* */
@@ -154,6 +156,17 @@ mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t 
  * membership is checked against the sector's list (safe lookup, Sec. IV).
  * k in 1..16.  The trie keeps a reference to `s`: destroy it before `s`. */
 mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
+
+/* The established methods the paper compares against (Sec. III, Sec. V.A).
+ * Bisection: lower bound of the pattern in the sector's ascending list, found
+ * when the entry equals the pattern; any sector; the ranker keeps a reference
+ * to `s` (destroy it first).  Combinadics: Eq. cns by the bit walk of Fig.
+ * algr (for the k-th set bit from the least significant end, at position c,
+ * add C(c, k)) for the particle-number sector of N out of M orbitals; ranks
+ * must fit 32 bits (ERANGE).  Both answer MBR_NOT_FOUND outside the sector. */
+mbr_status mbr_build_bisect_ranker(const mbr_sector *s, mbr_ranker **out);
+mbr_status mbr_build_cns_ranker(int32_t M, int32_t N, int32_t width_bits, mbr_ranker **out,
+                                void *stream);
 
 /* Layout of a trie ranker: *levels = number of levels (chunks), *lds_levels =
  * how many top levels each workgroup stages in LDS, entries[l] = uint32

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmbrank.so")
 NOT_FOUND = 0xFFFFFFFF
 
-RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED = 1, 2, 3, 4
+RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED, RANKER_BISECT, RANKER_CNS = 1, 2, 3, 4, 5, 6
 F64, F32 = 0, 1
 
 _lib = None
@@ -97,6 +97,9 @@ _SIGS = {
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mbr_build_bisect_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                         C.c_void_p]),
     "mbr_trie_level_entries": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                            C.POINTER(C.c_int32)]),
     "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -267,6 +270,19 @@ def build_trie(sector: Sector, k: int, stream=None) -> Ranker:
     h = C.c_void_p()
     _check("mbr_build_trie", lib().mbr_build_trie(sector.handle, k, C.byref(h), _stream(stream)))
     return Ranker(h, keep=(sector,))
+
+
+def build_bisect_ranker(sector: Sector) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_bisect_ranker", lib().mbr_build_bisect_ranker(sector.handle, C.byref(h)))
+    return Ranker(h, keep=(sector,))
+
+
+def build_cns_ranker(M: int, N: int, width_bits: int = 32, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_cns_ranker", lib().mbr_build_cns_ranker(M, N, width_bits, C.byref(h),
+                                                              _stream(stream)))
+    return Ranker(h)
 
 
 def trie_level_entries(ranker: Ranker):

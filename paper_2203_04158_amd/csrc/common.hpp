@@ -158,6 +158,10 @@ mbr_status rank_trie_launch(const mbr_ranker *r, const void *q, uint64_t n, uint
                             hipStream_t s);
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                hipStream_t s);
+mbr_status rank_bisect_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                              hipStream_t s);
+mbr_status rank_cns_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                           hipStream_t s);
 void trie_free(TrieLevels *t);
 uint64_t trie_bytes(const TrieLevels *t);
 int32_t trie_levels(const TrieLevels *t);
