@@ -13,6 +13,7 @@ The other workloads of the path are measured after the headline and reported
 under "rows" (kernel time by HIP events on the launch stream, each result
 checked for exactness or against stored oracle energies):
   staggered  sector M=24, N=12; 2^22 uniform member queries; k = 8
+  staggered64  M=64, N=32 with 64-bit patterns and ranks; 2^22 queries; k = 4, 8, 16
   trie       M=32, N=16 with >= 6 of orbitals 0-7 occupied (66,110,671 states);
              2^24 queries, 90% members and 10% non-members; k = 4 and 8
   learned    learned index vs trie vs spin-product staggered rank on the
@@ -47,7 +48,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
-ROWS = ("staggered", "trie", "learned", "batched")
+ROWS = ("staggered", "staggered64", "trie", "learned", "batched")
 EXTRA_ROWS = ("sweep",)   # run only when asked for by name
 
 
@@ -164,6 +165,33 @@ def row_staggered(torch, mbr, reps):
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
             "roofline": roof}
+
+
+def row_staggered64(torch, mbr, reps):
+    """64-bit patterns and ranks: M = 64, N = 32 (C(64,32) = 1.83e18 states, no
+    list can hold them); 2^22 queries; with 8-byte entries the table fits LDS
+    at k = 4 (49 KB) but not at k = 8 (377 KB) or 16 (44 MB), which are read
+    through the caches.  Checked by agreement of the three tables and by the
+    range of the ranks."""
+    import synth
+    M, N, nq = 64, 32, 1 << 22
+    base = synth.random_subset_patterns(64, 1 << 18, M, N)
+    q = torch.from_numpy(np.tile(base, nq // base.size).view(np.int64)).cuda()
+    res = {"workload": "M=64 N=32, 2^22 queries (2^18 distinct uniform 32-subsets), 64-bit ranks"}
+    outs = {}
+    for k in (4, 8, 16):
+        r = mbr.build_staggered_tables(M, N, k, width_bits=64)
+        out = torch.empty(nq, dtype=torch.int64, device="cuda")
+        ms = time_launches(torch, lambda: mbr.rank_batch64(r, q, out=out), reps)
+        outs[k] = out
+        roof = hbm_roofline(16.0 * nq, ms, f"rank_staggered_kernel, 64-bit (8 B in, 8 B out per query), k={k}")
+        res[f"k{k}"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
+                        "table_bytes": int(r.info().bytes), "roofline": roof}
+        del r
+    ranks = outs[8].cpu().numpy().view(np.uint64)
+    res["exact"] = (bool(torch.equal(outs[4], outs[8])) and bool(torch.equal(outs[8], outs[16]))
+                    and bool((ranks < np.uint64(math.comb(M, N))).all()))
+    return res
 
 
 def row_trie(torch, mbr, reps):
@@ -461,6 +489,8 @@ def main():
         t0 = time.perf_counter()
         if r == "staggered":
             extra[r] = row_staggered(torch, mbr, 50)
+        elif r == "staggered64":
+            extra[r] = row_staggered64(torch, mbr, 20)
         elif r == "trie":
             extra[r] = row_trie(torch, mbr, 20)
         elif r == "learned":

@@ -130,7 +130,9 @@ typedef struct {
  * the last chunk holds M mod k bits.  N >= 0 ranks within C^M_N (patterns of
  * other popcount rank to MBR_NOT_FOUND, Nmax = N); N = -1 builds the universal
  * table (Nmax = M) and ranks any pattern within its own particle-number block.
- * M in 1..64, k in 1..16, width_bits 32|64. */
+ * M in 1..64 (M <= 63 with N = -1), k in 1..16, width_bits 32|64.  When ranks
+ * can reach 2^32 - 1 (large M) they are only available through
+ * mbr_rank_batch64; mbr_rank_batch then returns ERANGE. */
 mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t width_bits,
                                       mbr_ranker **out, void *stream);
 
@@ -234,6 +236,12 @@ mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info);
  * MBR_NOT_FOUND.  d_q has the ranker's width. */
 mbr_status mbr_rank_batch(const mbr_ranker *r, const void *d_q, uint64_t n, uint32_t *d_rank,
                           void *stream);
+
+/* 64-bit ranks (Sec. III.B at M up to 64, where sectors exceed 2^32 states):
+ * d_rank[j] = rank of d_q[j], or all ones outside the sector.  Staggered
+ * rankers only (EUNSUPPORTED otherwise). */
+mbr_status mbr_rank_batch64(const mbr_ranker *r, const void *d_q, uint64_t n, uint64_t *d_rank,
+                            void *stream);
 
 mbr_status mbr_ranker_destroy(mbr_ranker *r);
 

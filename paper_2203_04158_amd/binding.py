@@ -97,6 +97,7 @@ _SIGS = {
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mbr_rank_batch64": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_build_bisect_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
                                          C.c_void_p]),
@@ -353,6 +354,17 @@ def rank_batch(ranker: Ranker, q, out=None, stream=None):
         out = torch.empty(q.numel(), dtype=torch.int32, device="cuda")
     _check("mbr_rank_batch", lib().mbr_rank_batch(ranker.handle, _dptr(q), q.numel(), _dptr(out),
                                                   _stream(stream)))
+    return out
+
+
+def rank_batch64(ranker: Ranker, q, out=None, stream=None):
+    """64-bit ranks of the patterns in q as an int64 tensor whose value -1 is
+    'not in the sector' (staggered rankers)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(q.numel(), dtype=torch.int64, device="cuda")
+    _check("mbr_rank_batch64", lib().mbr_rank_batch64(ranker.handle, _dptr(q), q.numel(), _dptr(out),
+                                                      _stream(stream)))
     return out
 
 

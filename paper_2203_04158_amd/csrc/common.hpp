@@ -140,6 +140,7 @@ struct mbr_ranker {
     int32_t N = -1;            // staggered: particle number or -1
     int32_t n_up = 0, n_dn = 0, L = 0;  // spin ranker
     uint64_t n_states = 0;
+    bool rank64 = false;       // staggered: ranks only fit the 64-bit entry point
     int device = 0;
     StagTable stag;            // staggered, spin halves
     TrieLevels *trie = nullptr;
@@ -158,6 +159,8 @@ mbr_status rank_trie_launch(const mbr_ranker *r, const void *q, uint64_t n, uint
                             hipStream_t s);
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                hipStream_t s);
+mbr_status rank_staggered_launch64(const mbr_ranker *r, const void *q, uint64_t n, uint64_t *out,
+                                   hipStream_t s);
 mbr_status rank_bisect_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                               hipStream_t s);
 mbr_status rank_cns_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,

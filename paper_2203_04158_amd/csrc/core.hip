@@ -154,6 +154,17 @@ mbr_status mbr_rank_batch(const mbr_ranker *r, const void *d_q, uint64_t n, uint
     }
 }
 
+mbr_status mbr_rank_batch64(const mbr_ranker *r, const void *d_q, uint64_t n, uint64_t *d_rank,
+                            void *stream) {
+    if (!r) MBR_FAIL(MBR_EINVAL, "null ranker");
+    if (n == 0) return MBR_OK;
+    if (!d_q || !d_rank) MBR_FAIL(MBR_EINVAL, "null query or output pointer");
+    if (n > (uint64_t)1 << 40) MBR_FAIL(MBR_ERANGE, "batch of %llu queries", (unsigned long long)n);
+    if (r->kind != MBR_RANKER_STAGGERED)
+        MBR_FAIL(MBR_EUNSUPPORTED, "64-bit ranks come from staggered rankers only");
+    return rank_staggered_launch64(r, d_q, n, d_rank, mbr::as_stream(stream));
+}
+
 mbr_status mbr_ranker_destroy(mbr_ranker *r) {
     delete r;
     return MBR_OK;

@@ -127,12 +127,12 @@ __device__ __forceinline__ void load_vec(const P *__restrict__ q, uint64_t j, P 
     }
 }
 
-template <int V>
-__device__ __forceinline__ void store_vec(uint32_t *__restrict__ out, uint64_t j, const uint32_t (&r)[V]) {
+template <class RT, int V>
+__device__ __forceinline__ void store_vec(RT *__restrict__ out, uint64_t j, const RT (&r)[V]) {
     if constexpr (V == 1) {
         out[j] = r[0];
     } else {
-        typedef uint32_t vec_t __attribute__((ext_vector_type(V)));
+        typedef RT vec_t __attribute__((ext_vector_type(V)));
         vec_t v;
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = r[i];
@@ -140,13 +140,14 @@ __device__ __forceinline__ void store_vec(uint32_t *__restrict__ out, uint64_t j
     }
 }
 
-// Rank of one query of a particle-number sector, MBR_NOT_FOUND outside it.
-template <class P, class E>
-__device__ __forceinline__ uint32_t stag_query(P x, const E *tab, const StagArgs &a) {
+// Rank of one query of a particle-number sector as RT (32 or 64 bits); all
+// ones (MBR_NOT_FOUND for 32 bits) outside it.
+template <class P, class E, class RT>
+__device__ __forceinline__ RT stag_query(P x, const E *tab, const StagArgs &a) {
     const int h = (sizeof(P) == 8) ? __popcll((uint64_t)x) : __popc((uint32_t)x);
     const bool ok = below_width(x, a.M) && (a.N < 0 || h == a.N);
     const uint64_t r = stag_rank<P, E>(ok ? x : (P)0, tab, a);  // 0 keeps every row in range
-    return ok ? (uint32_t)r : MBR_NOT_FOUND;
+    return ok ? (RT)r : (RT)~(RT)0;
 }
 
 // Queries are handled as vectors of V patterns, kVecs vectors per lane and
@@ -158,9 +159,9 @@ constexpr int kVecs = 4;
 
 // USE_LDS = false reads the table through the caches instead (tables larger
 // than the LDS budget, e.g. k = 16 or 64-bit patterns with wide chunks).
-template <class P, class E, bool USE_LDS, int V>
+template <class P, class E, bool USE_LDS, int V, class RT>
 __global__ void __launch_bounds__(kBlock) rank_staggered_kernel(const P *__restrict__ q, uint64_t n,
-                                                                uint32_t *__restrict__ out,
+                                                                RT *__restrict__ out,
                                                                 const E *__restrict__ gtab,
                                                                 StagArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -188,16 +189,16 @@ __global__ void __launch_bounds__(kBlock) rank_staggered_kernel(const P *__restr
         for (int u = 0; u < kVecs; ++u) {
             const uint64_t j = base + u * stride;
             if (j < nv) {
-                uint32_t r[V];
+                RT r[V];
 #pragma unroll
-                for (int i = 0; i < V; ++i) r[i] = stag_query<P, E>(x[u][i], tab, a);
-                store_vec<V>(out, j, r);
+                for (int i = 0; i < V; ++i) r[i] = stag_query<P, E, RT>(x[u][i], tab, a);
+                store_vec<RT, V>(out, j, r);
             }
         }
     }
     if (t0 < n - nv * V) {
         const uint64_t j = nv * V + t0;
-        out[j] = stag_query<P, E>(q[j], tab, a);
+        out[j] = stag_query<P, E, RT>(q[j], tab, a);
     }
 }
 
@@ -258,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) rank_spin_kernel(const P *__restrict__
                 uint32_t r[V];
 #pragma unroll
                 for (int i = 0; i < V; ++i) r[i] = spin_query<P, E>(x[u][i], tab, a);
-                store_vec<V>(out, j, r);
+                store_vec<uint32_t, V>(out, j, r);
             }
         }
     }
@@ -292,35 +293,33 @@ mbr_status set_lds(K kernel, size_t bytes) {
 
 // Vector width for a launch: 16-byte accesses when both the queries and the
 // ranks are aligned to them, otherwise one pattern per access.
-template <class P>
-bool vec_aligned(const void *q, const uint32_t *out) {
+template <class P, class RT = uint32_t>
+bool vec_aligned(const void *q, const RT *out) {
     constexpr int V = 16 / sizeof(P);
-    return ((uintptr_t)q % 16 == 0) && ((uintptr_t)out % (4 * V) == 0);
+    return ((uintptr_t)q % 16 == 0) && ((uintptr_t)out % (sizeof(RT) * V) == 0);
 }
 
-template <class P, class E, int V>
-mbr_status launch_stag_v(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
-                         hipStream_t s) {
+template <class P, class E, int V, class RT>
+mbr_status launch_stag_v(const mbr_ranker *r, const void *q, uint64_t n, RT *out, hipStream_t s) {
     StagArgs a = make_args(r->stag, r->N);
     size_t lds = a.nentries * sizeof(E);
     unsigned grid = mbr::grid_for((n + V - 1) / V, kBlock * kVecs, mbr::device_cu_count() * 8);
     if (lds <= kLdsTable) {
-        auto kern = rank_staggered_kernel<P, E, true, V>;
+        auto kern = rank_staggered_kernel<P, E, true, V, RT>;
         MBR_TRY(set_lds(kern, lds));
         kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
     } else {
-        rank_staggered_kernel<P, E, false, V><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
-                                                                     r->stag.table.as<E>(), a);
+        rank_staggered_kernel<P, E, false, V, RT><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
+                                                                         r->stag.table.as<E>(), a);
     }
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
 
-template <class P, class E>
-mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
-                       hipStream_t s) {
-    if (vec_aligned<P>(q, out)) return launch_stag_v<P, E, 16 / sizeof(P)>(r, q, n, out, s);
-    return launch_stag_v<P, E, 1>(r, q, n, out, s);
+template <class P, class E, class RT>
+mbr_status launch_stag(const mbr_ranker *r, const void *q, uint64_t n, RT *out, hipStream_t s) {
+    if (vec_aligned<P, RT>(q, out)) return launch_stag_v<P, E, 16 / sizeof(P), RT>(r, q, n, out, s);
+    return launch_stag_v<P, E, 1, RT>(r, q, n, out, s);
 }
 
 template <class P, class E, int V>
@@ -357,6 +356,20 @@ mbr_status launch_spin(const mbr_ranker *r, const void *q, uint64_t n, uint32_t 
 
 mbr_status rank_staggered_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                  hipStream_t s) {
+    if (r->rank64) MBR_FAIL(MBR_ERANGE, "ranks of this sector need 64 bits: use mbr_rank_batch64");
+    int eb = r->stag.entry_bytes;
+    if (r->width_bits == 32) {
+        if (eb == 2) return launch_stag<uint32_t, uint16_t>(r, q, n, out, s);
+        if (eb == 4) return launch_stag<uint32_t, uint32_t>(r, q, n, out, s);
+        return launch_stag<uint32_t, uint64_t>(r, q, n, out, s);
+    }
+    if (eb == 2) return launch_stag<uint64_t, uint16_t>(r, q, n, out, s);
+    if (eb == 4) return launch_stag<uint64_t, uint32_t>(r, q, n, out, s);
+    return launch_stag<uint64_t, uint64_t>(r, q, n, out, s);
+}
+
+mbr_status rank_staggered_launch64(const mbr_ranker *r, const void *q, uint64_t n, uint64_t *out,
+                                   hipStream_t s) {
     int eb = r->stag.entry_bytes;
     if (r->width_bits == 32) {
         if (eb == 2) return launch_stag<uint32_t, uint16_t>(r, q, n, out, s);
@@ -404,7 +417,7 @@ mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t w
     int nmax = N < 0 ? M : N;
     uint64_t worst = 0;
     for (int n = (N < 0 ? 0 : N); n <= (N < 0 ? M : N); ++n) worst = binom(M, n) > worst ? binom(M, n) : worst;
-    if (worst >= 0xFFFFFFFFull) MBR_FAIL(MBR_ERANGE, "ranks up to %llu do not fit 32 bits", (unsigned long long)worst);
+    if (M == 64 && N < 0) MBR_FAIL(MBR_ERANGE, "a universal table at M=64 holds 2^64 states");
     auto *r = new (std::nothrow) mbr_ranker;
     if (!r) MBR_FAIL(MBR_ENOMEM, "host allocation");
     r->kind = MBR_RANKER_STAGGERED;
@@ -412,7 +425,8 @@ mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t w
     r->k = k;
     r->N = N;
     r->width_bits = width_bits;
-    r->n_states = N < 0 ? ((M >= 64) ? ~0ull : (1ull << M)) : binom(M, N);
+    r->n_states = N < 0 ? (1ull << M) : binom(M, N);
+    r->rank64 = worst >= 0xFFFFFFFFull;  // ranks need the 64-bit entry point
     (void)hipGetDevice(&r->device);
     if (((uint64_t)(nch * (nmax + 1)) << k) > (1ull << 26))
         MBR_FAIL_DEL(r, MBR_EUNSUPPORTED, "staggered table beyond 2^26 entries");

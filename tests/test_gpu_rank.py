@@ -101,16 +101,34 @@ def test_staggered_against_cns(M, N, k):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("M,N,k", [(40, 20, 8), (64, 32, 8), (64, 5, 13), (48, 24, 16)])
+@pytest.mark.parametrize("M,N,k", [(40, 20, 8), (64, 32, 8), (64, 5, 13), (48, 24, 16), (64, 32, 16),
+                                   (64, 63, 4), (50, 25, 7)])
 def test_staggered_u64(M, N, k):
+    """64-bit patterns; sectors of 2^32 states or more rank through the 64-bit
+    entry point (the 32-bit one refuses them), against Eq. cns on the host."""
+    import torch
     q = synth.random_subset_patterns(M + N + k, 40000, M, N)
+    noise = synth.splitmix64(M * 3 + k, 20000)
+    if M < 64:
+        noise &= np.uint64((1 << M) - 1)
+    q = np.concatenate([q, noise])
+    pc = np.array([bin(int(a)).count("1") for a in q])
+    inw = (q >> np.uint64(M)) == 0 if M < 64 else np.ones(q.size, bool)
+    member = (pc == N) & inw
+    r = mbr.build_staggered_tables(M, N, k, width_bits=64)
+    want64 = np.where(member, OC.cns_rank_batch(q), np.uint64(0xFFFFFFFFFFFFFFFF))
+    got64 = mbr.rank_batch64(r, dev_u64(q)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got64, want64)
     if math.comb(M, N) >= 2 ** 32 - 1:
         with pytest.raises(mbr.MbrError):
-            mbr.build_staggered_tables(M, N, k, width_bits=64)
-        return
-    r = mbr.build_staggered_tables(M, N, k, width_bits=64)
-    got = host_rank(mbr.rank_batch(r, dev_u64(q)))
-    assert np.array_equal(got, OC.cns_rank_batch(q).astype(np.int64))
+            mbr.rank_batch(r, dev_u64(q))
+    else:
+        got = host_rank(mbr.rank_batch(r, dev_u64(q)))
+        assert np.array_equal(got, np.where(member, OC.cns_rank_batch(q).astype(np.int64), -1))
+    # unaligned 64-bit rank output, ragged length
+    out = torch.zeros(q.size + 1, dtype=torch.int64, device="cuda")[1:]
+    mbr.rank_batch64(r, dev_u64(q), out=out)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), want64)
 
 
 @pytest.mark.parametrize("L,nu,nd,k", [(14, 7, 7, 7), (14, 7, 7, 14), (12, 3, 8, 5), (4, 1, 2, 2),
