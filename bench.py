@@ -23,6 +23,8 @@ checked for exactness or against stored oracle energies):
              (N_up, N_dn) sectors, 150 steps with full reorthogonalisation:
              batched graph-captured steps with fp32 vectors against per-sector
              launches with fp64 vectors
+  operator   generic term-tuple H·x on the momentum-space Hubbard ring, L = 14,
+             (7,7), total momentum 0, trie ranks
   sweep      (by name only) the ranking microbenchmark of Sec. V.A: M = 28,
              N = 1..27, sorted queries, bisection / combinadics / staggered /
              trie at R = 4, 8, 12
@@ -48,7 +50,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
-ROWS = ("staggered", "staggered64", "trie", "learned", "batched")
+ROWS = ("staggered", "staggered64", "trie", "learned", "batched", "operator")
 EXTRA_ROWS = ("sweep",)   # run only when asked for by name
 
 
@@ -315,6 +317,42 @@ def row_sweep(torch, mbr, reps):
             "half_filled_granks_per_s": {m: 1.0 / ns[m][13] for m in methods}}
 
 
+def row_operator(torch, mbr, reps):
+    """Generic term-tuple H·x (Eq. H -> tuples by App. A, gather form of
+    Eq. Talpha2) on the momentum-space Hubbard ring of Sec. V.C: L = 14
+    momenta per spin (M = 28), U = 4, sector (7,7) with total momentum 0,
+    ranked by a trie (the sector is irregular: no closed-form rank).  The
+    interaction has L^3 momentum-conserving terms."""
+    import synth
+    L, U, K = 14, 4.0, 0
+    M = 2 * L
+    t = np.zeros((M, M))
+    for k in range(L):
+        t[k, k] = t[L + k, L + k] = 2.0 * math.cos(2 * math.pi * k / L)   # -eps_k
+    cl = [(L + k1, k2, L + (k1 + k2 - k3) % L, k3, 4.0 * U / L)
+          for k1 in range(L) for k2 in range(L) for k3 in range(L)]
+    terms = mbr.terms_from_hamiltonian(M, t, cl)
+    cons = [(0x3FFF, 7, 7), (0x3FFF << 14, 7, 7)]
+    sec = mbr.sector_build_mod(M, cons, list(range(L)) * 2, L, K)
+    res = {"workload": f"momentum-space Hubbard ring L={L}, U={U}, sector (7,7) K={K} "
+                       f"({sec.size:,} states), {len(terms)} tuples",
+           "n_states": sec.size, "n_terms": len(terms)}
+    x = torch.from_numpy(2 * synth.uniform01(6, sec.size) - 1).cuda()
+    ys = {}
+    for k in (7, 14):
+        r = mbr.build_trie(sec, k)
+        op = mbr.operator_create(sec, r, terms)
+        y = torch.empty_like(x)
+        ms = time_launches(torch, lambda: mbr.operator_apply(op, x, y), reps)
+        ys[k] = y
+        res[f"trie_k{k}"] = {"value": 1e3 / ms, "unit": "H·v/s", "kernel_ms": ms,
+                             "term_checks_per_s": len(terms) * sec.size / (ms * 1e-3),
+                             "trie_bytes": int(r.info().bytes)}
+        del op, r
+    res["exact"] = bool(torch.equal(ys[7], ys[14]))  # two trie layouts, identical sums
+    return res
+
+
 def row_batched(torch, mbr, steps: int):
     """Anderson impurity model, all 169 sectors, `steps` Lanczos steps with full
     reorthogonalisation: batched + graph + fp32 vectors against per-sector
@@ -497,6 +535,8 @@ def main():
             extra[r] = row_learned(torch, mbr, 20, big=not args.no_big)
         elif r == "batched":
             extra[r] = row_batched(torch, mbr, 150)
+        elif r == "operator":
+            extra[r] = row_operator(torch, mbr, 5)
         elif r == "sweep":
             extra[r] = row_sweep(torch, mbr, 10)
         extra[r]["wall_s"] = time.perf_counter() - t0

@@ -85,6 +85,15 @@ typedef struct mbr_sector mbr_sector;
 mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
                             const mbr_popc_cons *cons, mbr_sector **out, void *stream);
 
+/* As mbr_sector_build, plus one modular constraint: the weights of the set
+ * bits add up to `residue` modulo `modulus` (weights[i] for orbital i, M
+ * entries).  With orbital weights equal to lattice momenta this gives the
+ * total-momentum sectors of a translation-invariant ring (Sec. V.C, the
+ * K_tot sets of Sec. IV). */
+mbr_status mbr_sector_build_mod(int32_t M, int32_t width_bits, int32_t n_cons, const mbr_popc_cons *cons,
+                                const int32_t *weights, int32_t modulus, int32_t residue,
+                                mbr_sector **out, void *stream);
+
 /* Number of states in the sector. */
 mbr_status mbr_sector_size(const mbr_sector *s, uint64_t *n);
 
@@ -244,6 +253,52 @@ mbr_status mbr_rank_batch64(const mbr_ranker *r, const void *d_q, uint64_t n, ui
                             void *stream);
 
 mbr_status mbr_ranker_destroy(mbr_ranker *r);
+
+/* ======================================================================== */
+/* General operators from non-branching terms (Sec. II, Eq. H, App. A)       */
+/* ======================================================================== */
+
+/* One term as the tuple of Eq. Talpha1 / Eq. Talpha2:
+ *   T|a> = v [a & m == r] (-1)^popcount(a & s) |a ^ x>,
+ *   <a|T = v [a & m == l] (-1)^popcount(a & s) <a ^ x|. */
+typedef struct {
+    double v;
+    uint64_t m, l, r, x, s;
+} mbr_term;
+
+/* Two-body coefficient U_ijkl of Eq. H (the term (1/4) U c+_i c+_j c_l c_k). */
+typedef struct {
+    int32_t i, j, k, l;
+    double U;
+} mbr_coulomb;
+
+typedef struct mbr_operator mbr_operator;
+
+/* Tuples of H = -sum_ij t_ij c+_i c_j + 1/4 sum U_ijkl c+_i c+_j c_l c_k (Eq. H)
+ * over M orbitals: each term's tuple is built from those of c_i and c+_i
+ * (Eqs. ci) by the product rule of App. A, terms with equal (m, l, x, s) are
+ * merged by adding their prefactors and zero terms are dropped.  t is M*M
+ * row-major (NULL: no one-body part); u holds n_u two-body entries.  *n_out
+ * receives the number of tuples; they are written to out when cap suffices.
+ * Host only. */
+mbr_status mbr_terms_from_hamiltonian(int32_t M, const double *t, int32_t n_u, const mbr_coulomb *u,
+                                      mbr_term *out, int64_t cap, int64_t *n_out);
+
+/* An operator on one sector: the term list (copied to the device) and a
+ * ranker for that sector, either a staggered ranker of the same C^M_N (the
+ * sector built with the single window of N set bits among all M orbitals) or
+ * a trie built on `s`.  y = H x is formed in gather form (Eq. Talpha2), one lane
+ * per row: y_a = sum_T v [a & m == l] (-1)^popcount(a & s) x[rank(a ^ x_T)];
+ * terms that lead out of the sector contribute nothing.  The operator keeps
+ * references to `s` and `r`. */
+mbr_status mbr_operator_create(const mbr_sector *s, const mbr_ranker *r, const mbr_term *terms,
+                               int64_t n_terms, mbr_operator **out, void *stream);
+
+/* y = H x over the sector, fp64 vectors of the sector's size (d_x and d_y must
+ * not alias). */
+mbr_status mbr_operator_apply(const mbr_operator *op, const double *d_x, double *d_y, void *stream);
+
+mbr_status mbr_operator_destroy(mbr_operator *op);
 
 /* ======================================================================== */
 /* Hubbard-type Hamiltonians applied on the fly (Eq. Talpha, Eq. mvblock,     */

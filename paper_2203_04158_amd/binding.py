@@ -49,6 +49,16 @@ class LearnedInfo(C.Structure):
                 ("single_window_error", C.c_uint64), ("uses_window", C.c_int32)]
 
 
+class Term(C.Structure):
+    _fields_ = [("v", C.c_double), ("m", C.c_uint64), ("l", C.c_uint64), ("r", C.c_uint64),
+                ("x", C.c_uint64), ("s", C.c_uint64)]
+
+
+class Coulomb(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k", C.c_int32), ("l", C.c_int32),
+                ("U", C.c_double)]
+
+
 class Bond(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("t", C.c_double)]
 
@@ -97,6 +107,14 @@ _SIGS = {
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mbr_sector_build_mod": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_terms_from_hamiltonian": (C.c_int32, [C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_int64, C.POINTER(C.c_int64)]),
+    "mbr_operator_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_operator_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_operator_destroy": (C.c_int32, [C.c_void_p]),
     "mbr_rank_batch64": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_build_bisect_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
@@ -207,6 +225,18 @@ def sector_build(M: int, constraints, width_bits: int = 32, stream=None) -> Sect
     h = C.c_void_p()
     _check("mbr_sector_build", lib().mbr_sector_build(M, width_bits, len(cons), arr, C.byref(h),
                                                       _stream(stream)))
+    return Sector(h, M, width_bits)
+
+
+def sector_build_mod(M: int, constraints, weights, modulus: int, residue: int, width_bits: int = 32,
+                     stream=None) -> Sector:
+    """Popcount windows plus sum(weights of set bits) = residue (mod modulus)."""
+    cons = list(constraints)
+    arr = (PopcCons * max(1, len(cons)))(*[PopcCons(int(m), int(lo), int(hi)) for m, lo, hi in cons])
+    w = (C.c_int32 * M)(*[int(v) for v in weights])
+    h = C.c_void_p()
+    _check("mbr_sector_build_mod", lib().mbr_sector_build_mod(M, width_bits, len(cons), arr, w, modulus,
+                                                              residue, C.byref(h), _stream(stream)))
     return Sector(h, M, width_bits)
 
 
@@ -366,6 +396,60 @@ def rank_batch64(ranker: Ranker, q, out=None, stream=None):
     _check("mbr_rank_batch64", lib().mbr_rank_batch64(ranker.handle, _dptr(q), q.numel(), _dptr(out),
                                                       _stream(stream)))
     return out
+
+
+# --------------------------------------------------------------------------- general operators
+def terms_from_hamiltonian(M: int, t=None, coulomb=()):
+    """Tuples of Eq. H: t is an M x M array (or None), coulomb an iterable of
+    (i, j, k, l, U).  Returns a list of (v, m, l, r, x, s)."""
+    tt = None
+    if t is not None:
+        tt = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(M, M))
+    cl = list(coulomb)
+    carr = (Coulomb * max(1, len(cl)))(*[Coulomb(int(i), int(j), int(k), int(l), float(u))
+                                         for i, j, k, l, u in cl])
+    n = C.c_int64()
+    tp = C.c_void_p(tt.ctypes.data) if tt is not None else None
+    L = lib()
+    _check("mbr_terms_from_hamiltonian", L.mbr_terms_from_hamiltonian(M, tp, len(cl), carr, None, 0,
+                                                                      C.byref(n)))
+    out = (Term * max(1, n.value))()
+    _check("mbr_terms_from_hamiltonian", L.mbr_terms_from_hamiltonian(M, tp, len(cl), carr, out,
+                                                                      n.value, C.byref(n)))
+    return [(o.v, o.m, o.l, o.r, o.x, o.s) for o in out[: n.value]]
+
+
+class Operator:
+    def __init__(self, handle, sector: Sector, ranker: Ranker, n_terms: int):
+        self._h = handle
+        self._keep = (sector, ranker)
+        self.dim = sector.size
+        self.n_terms = n_terms
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mbr_operator_destroy(self._h)
+            self._h = None
+
+
+def operator_create(sector: Sector, ranker: Ranker, terms, stream=None) -> Operator:
+    """terms: list of (v, m, l, r, x, s) tuples."""
+    tl = list(terms)
+    arr = (Term * max(1, len(tl)))(*[Term(float(v), int(m), int(l), int(r), int(x), int(s))
+                                     for v, m, l, r, x, s in tl])
+    h = C.c_void_p()
+    _check("mbr_operator_create", lib().mbr_operator_create(sector.handle, ranker.handle, arr, len(tl),
+                                                            C.byref(h), _stream(stream)))
+    return Operator(h, sector, ranker, len(tl))
+
+
+def operator_apply(op: Operator, x, y, stream=None):
+    _check("mbr_operator_apply", lib().mbr_operator_apply(op.handle, _dptr(x), _dptr(y), _stream(stream)))
+    return y
 
 
 # --------------------------------------------------------------------------- Hamiltonian

@@ -115,6 +115,7 @@ struct mbr_sector {
     uint64_t n = 0;
     int device = 0;
     std::vector<mbr_popc_cons> cons;
+    int32_t modulus = 0, residue = 0;  // modular weight constraint (modulus 0: none)
     mbr::DevBuf states;
 };
 
@@ -131,7 +132,18 @@ struct StagTable {
 mbr_status stag_build(StagTable &t, int32_t M, int32_t k, int32_t nmax, int32_t entry_bytes,
                       hipStream_t stream);
 
-struct TrieLevels;
+// Packed trie, one uint32 array per level (level-major layout of trie.hip).
+struct TrieLevels {
+    int32_t M = 0, H = 0, width_bits = 32;
+    int32_t w[64] = {0};       // chunk widths, least significant first
+    int32_t shift[64] = {0};   // bit offset of chunk l in the pattern
+    uint64_t off[65] = {0};    // level l occupies entries off[l] .. off[l+1]-1
+    uint64_t entries = 0;
+    uint64_t lds_levels = 0;   // levels 0..lds_levels-1 are staged in LDS
+    uint64_t lds_entries = 0;
+    mbr::DevBuf table;         // uint32 entries of all levels
+};
+
 struct LearnedModel;
 
 struct mbr_ranker {

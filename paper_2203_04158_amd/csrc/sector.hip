@@ -21,6 +21,8 @@ struct ConsSet {
     int32_t lo[kMaxCons];
     int32_t hi[kMaxCons];
     int32_t n;
+    int32_t modulus, residue;  // modulus > 0: sum of the weights of the set bits = residue (mod modulus)
+    int32_t weight[64];
 };
 
 __device__ __forceinline__ bool in_sector(uint64_t a, const ConsSet &cs) {
@@ -28,6 +30,13 @@ __device__ __forceinline__ bool in_sector(uint64_t a, const ConsSet &cs) {
     for (int j = 0; j < cs.n; ++j) {
         int h = __popcll(a & cs.mask[j]);
         ok = ok && (h >= cs.lo[j]) && (h <= cs.hi[j]);
+    }
+    if (ok && cs.modulus > 0) {
+        int64_t w = 0;
+        for (uint64_t m = a; m; m &= m - 1) w += cs.weight[__builtin_ctzll(m)];
+        int64_t r = w % cs.modulus;
+        if (r < 0) r += cs.modulus;
+        ok = r == cs.residue;
     }
     return ok;
 }
@@ -124,12 +133,9 @@ int implied_n(int M, const std::vector<mbr_popc_cons> &cons) {
     return covered == full ? n : -1;
 }
 
-}  // namespace
-
-extern "C" {
-
-mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
-                            const mbr_popc_cons *cons, mbr_sector **out, void *stream) {
+mbr_status sector_build_impl(int32_t M, int32_t width_bits, int32_t n_cons, const mbr_popc_cons *cons,
+                             const int32_t *weights, int32_t modulus, int32_t residue, mbr_sector **out,
+                             void *stream) {
     using namespace mbr;
     if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
     *out = nullptr;
@@ -144,6 +150,8 @@ mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
         if (c.mask & ~full) MBR_FAIL(MBR_EINVAL, "constraint mask has bits at or above M");
         if (c.lo < 0 || c.hi < c.lo || c.hi > 64) MBR_FAIL(MBR_EINVAL, "constraint window [%d,%d]", c.lo, c.hi);
     }
+    if (modulus < 0 || (modulus > 0 && (!weights || residue < 0 || residue >= modulus)))
+        MBR_FAIL(MBR_EINVAL, "modular constraint: modulus %d, residue %d", modulus, residue);
     int N = implied_n(M, cv);
     uint64_t S;
     if (N >= 0) {
@@ -168,6 +176,9 @@ mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
         cs.lo[j] = cv[j].lo;
         cs.hi[j] = cv[j].hi;
     }
+    cs.modulus = modulus;
+    cs.residue = residue;
+    for (int i = 0; i < M && modulus > 0; ++i) cs.weight[i] = weights[i] % modulus;
     DevBuf d_counts, d_off;
     MBR_TRY(d_counts.alloc(nruns * sizeof(uint32_t)));
     unsigned blk = 256;
@@ -194,6 +205,8 @@ mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
     sec->width_bits = width_bits;
     sec->n = total;
     sec->cons = cv;
+    sec->modulus = modulus;
+    sec->residue = residue;
     MBR_HIP(hipGetDevice(&sec->device));
     mbr_status st = sec->states.alloc(total * (width_bits / 8));
     if (st == MBR_OK) st = upload(d_off, off.data(), nruns * sizeof(uint64_t), s);
@@ -222,6 +235,22 @@ mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
     }
     *out = sec;
     return MBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbr_status mbr_sector_build(int32_t M, int32_t width_bits, int32_t n_cons,
+                            const mbr_popc_cons *cons, mbr_sector **out, void *stream) {
+    return sector_build_impl(M, width_bits, n_cons, cons, nullptr, 0, 0, out, stream);
+}
+
+mbr_status mbr_sector_build_mod(int32_t M, int32_t width_bits, int32_t n_cons, const mbr_popc_cons *cons,
+                                const int32_t *weights, int32_t modulus, int32_t residue,
+                                mbr_sector **out, void *stream) {
+    if (modulus < 1) MBR_FAIL(MBR_EINVAL, "modulus %d must be positive", modulus);
+    return sector_build_impl(M, width_bits, n_cons, cons, weights, modulus, residue, out, stream);
 }
 
 mbr_status mbr_sector_size(const mbr_sector *s, uint64_t *n) {

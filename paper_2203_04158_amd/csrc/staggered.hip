@@ -6,7 +6,7 @@
 // recommends so that only the rows a query touches are loaded).  A workgroup
 // copies the whole table into LDS once and then ranks a grid-stride share of
 // the queries: per query, ceil(M/k) dependent LDS reads and popcounts.
-#include "common.hpp"
+#include "rank_device.hpp"
 
 // ------------------------------------------------------------------ tables
 
@@ -76,35 +76,7 @@ int entry_bytes_for(int M, int nmax) {
     return 8;
 }
 
-struct StagArgs {
-    int32_t M, k, nch, N;
-    int32_t rowoff[16];
-    uint64_t nentries;
-};
-
 constexpr unsigned kBlock = 256;
-
-template <class P>
-__device__ __forceinline__ bool below_width(P x, int M) {
-    return (M >= (int)(8 * sizeof(P))) ? true : (x >> M) == 0;
-}
-
-// Rank of the low `bits` bits of x within its own particle-number block,
-// Fig. fastrank: add the partial rank of each k-bit chunk, advancing N' by
-// the chunk's popcount.  `tab` is the LDS copy of the table.
-template <class P, class E>
-__device__ __forceinline__ uint64_t stag_rank(P x, const E *tab, const StagArgs &a) {
-    uint64_t rank = 0;
-    int np = 0;
-    const P cm = (P)((1ull << a.k) - 1);
-#pragma unroll 4
-    for (int c = 0; c < a.nch; ++c) {
-        P r = (x >> (c * a.k)) & cm;
-        rank += (uint64_t)tab[((uint32_t)(a.rowoff[c] + np) << a.k) + (uint32_t)r];
-        np += (sizeof(P) == 8) ? __popcll((uint64_t)r) : __popc((uint32_t)r);
-    }
-    return rank;
-}
 
 template <class E>
 __device__ __forceinline__ void load_table(E *lds, const E *__restrict__ g, uint64_t n) {

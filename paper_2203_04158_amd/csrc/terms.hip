@@ -1,0 +1,327 @@
+// Generic operators from non-branching terms (App. A) applied on the fly.
+//
+// Every term of Eq. H, a prefactor times a product of creation and
+// annihilation operators, acts on an occupation pattern as one tuple
+// (v, m, l, r, x, s) (Eq. Talpha1, Eq. Talpha2).  Tuples are built on the host
+// from those of the single operators (Eqs. ci) by the product rule of App. A;
+// terms with equal (m, l, x, s) are merged by adding their prefactors.
+//
+// The product is taken in gather form from the bra side (Eq. Talpha2), one
+// lane per output row, so no atomics are needed:
+//   y_alpha = sum_T v [alpha AND m == l] (-1)^popcount(alpha AND s) x[rank(alpha XOR x_T)]
+// with alpha = states[row] and the rank from the operator's ranker: a staggered
+// table (sector C^M_N; table staged in LDS when it fits) or a packed trie (any
+// sector; walk plus membership check).  Tuples are uniform across the lanes
+// and are read through the scalar path.
+#include <algorithm>
+#include <memory>
+#include <tuple>
+
+#include "rank_device.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------- host algebra
+struct Tup {
+    double v;
+    uint64_t m, l, r, x, s;
+};
+
+// c_i (Eqs. ci): needs orbital i occupied on the right, leaves it empty on the
+// left, flips it, and picks up the parity of the orbitals below i.
+Tup annihilator(int i) {
+    const uint64_t b = 1ull << i;
+    return Tup{1.0, b, 0, b, b, b - 1};
+}
+
+// c_i^dagger: the annihilator with its left and right requirements exchanged.
+Tup creator(int i) {
+    Tup t = annihilator(i);
+    std::swap(t.l, t.r);
+    return t;
+}
+
+// Tuple of the product T_a T_b (T_b acts first), App. A.  Restated:
+//  * on the orbitals of m_b the state must equal r_b; T_b leaves them at l_b.
+//    T_a then demands r_a on m_a, so where the masks overlap l_b must equal
+//    r_a (else the product vanishes), and on m_a outside m_b the original
+//    state must already hold r_a:  r = r_b | (r_a & ~m_b);
+//  * afterwards m_a holds l_a and the rest of m_b still holds l_b:
+//    l = l_a | (l_b & ~m_a), and the flipped orbitals are x = l ^ r;
+//  * the sign of T_b counts alpha & s_b, that of T_a the intermediate state &
+//    s_a.  Outside m both states equal alpha, giving the mask (s_a ^ s_b) & ~m;
+//    inside m they are fixed (r, then r ^ x_b), so their parity is a constant
+//    folded into v.
+Tup product(const Tup &a, const Tup &b) {
+    Tup t;
+    const bool clash = ((a.r ^ b.l) & a.m & b.m) != 0;
+    t.m = a.m | b.m;
+    t.r = b.r | (a.r & ~b.m);
+    t.l = a.l | (b.l & ~a.m);
+    t.x = t.l ^ t.r;
+    t.s = (a.s ^ b.s) & ~t.m;
+    const uint64_t before = t.r, between = t.r ^ b.x;  // the state inside m before T_b and before T_a
+    const int parity = (__builtin_popcountll(before & b.s) + __builtin_popcountll(between & a.s)) & 1;
+    t.v = clash ? 0.0 : (parity ? -a.v * b.v : a.v * b.v);
+    return t;
+}
+
+Tup product_of(double v, std::initializer_list<Tup> ops) {
+    auto it = ops.begin();
+    Tup t = *it;
+    for (++it; it != ops.end(); ++it) t = product(t, *it);
+    t.v *= v;
+    return t;
+}
+
+// Merge tuples with equal (m, l, x, s), drop zeros; deterministic order.
+std::vector<Tup> merge_terms(std::vector<Tup> ts) {
+    std::sort(ts.begin(), ts.end(), [](const Tup &a, const Tup &b) {
+        return std::tie(a.m, a.l, a.x, a.s) < std::tie(b.m, b.l, b.x, b.s);
+    });
+    std::vector<Tup> out;
+    for (const Tup &t : ts) {
+        if (!out.empty() && out.back().m == t.m && out.back().l == t.l && out.back().x == t.x &&
+            out.back().s == t.s)
+            out.back().v += t.v;
+        else
+            out.push_back(t);
+    }
+    out.erase(std::remove_if(out.begin(), out.end(), [](const Tup &t) { return t.v == 0.0; }), out.end());
+    return out;
+}
+
+// ---------------------------------------------------------------- device apply
+constexpr unsigned kBlock = 256;
+constexpr size_t kLdsTable = 64 * 1024;
+
+enum RankKind { kStagLds = 0, kStagGlobal = 1, kTrie = 2 };
+
+template <class P>
+struct OpArgs {
+    const P *states;
+    uint64_t ns;
+    int64_t nt;
+    const double *v;
+    const P *m, *l, *x, *s;
+    const double *xin;
+    double *out;
+    StagArgs stag;
+    const void *stab;
+    TrieWalk trie;
+};
+
+template <class P, class E, int RK>
+__global__ void __launch_bounds__(kBlock) op_apply_kernel(OpArgs<P> a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const E *tab = static_cast<const E *>(a.stab);
+    if constexpr (RK == kStagLds) {
+        E *t = reinterpret_cast<E *>(lds_raw);
+        for (uint64_t i = threadIdx.x; i < a.stag.nentries; i += blockDim.x) t[i] = tab[i];
+        __syncthreads();
+        tab = t;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t row = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; row < a.ns; row += stride) {
+        const P al = a.states[row];
+        double acc = 0.0;
+        for (int64_t t = 0; t < a.nt; ++t) {
+            if ((al & a.m[t]) != a.l[t]) continue;
+            const P be = al ^ a.x[t];
+            uint64_t rr;
+            if (a.x[t] == 0) {
+                rr = row;
+            } else if constexpr (RK == kTrie) {
+                const uint32_t q = trie_rank_one<P>(be, a.trie);
+                if (q == MBR_NOT_FOUND) continue;  // the term leaves the sector
+                rr = q;
+            } else {
+                const int h = (sizeof(P) == 8) ? __popcll((uint64_t)be) : __popc((uint32_t)be);
+                if (h != a.stag.N || !below_width(be, a.stag.M)) continue;  // leaves C^M_N
+                rr = stag_rank<P, E>(be, tab, a.stag);
+            }
+            const bool odd = ((sizeof(P) == 8) ? __popcll((uint64_t)(al & a.s[t])) : __popc((uint32_t)(al & a.s[t]))) & 1;
+            const double c = odd ? -a.v[t] : a.v[t];
+            acc = __builtin_fma(c, a.xin[rr], acc);
+        }
+        a.out[row] = acc;
+    }
+}
+
+}  // namespace
+
+struct mbr_operator {
+    const mbr_sector *sec = nullptr;
+    const mbr_ranker *rk = nullptr;
+    int64_t nt = 0;
+    int32_t M = 0, width_bits = 32;
+    mbr::DevBuf v, m, l, x, s;
+    int device = 0;
+};
+
+namespace {
+
+template <class P, class E, int RK>
+mbr_status launch_op(const mbr_operator *op, OpArgs<P> a, size_t lds, hipStream_t st) {
+    auto kern = op_apply_kernel<P, E, RK>;
+    if (lds > 64 * 1024)
+        MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const unsigned grid = mbr::grid_for(op->sec->n, kBlock, mbr::device_cu_count() * 8);
+    kern<<<grid, kBlock, lds, st>>>(a);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+template <class P>
+mbr_status apply_t(const mbr_operator *op, const double *x, double *y, hipStream_t st) {
+    OpArgs<P> a{};
+    a.states = op->sec->states.as<P>();
+    a.ns = op->sec->n;
+    a.nt = op->nt;
+    a.v = op->v.as<double>();
+    a.m = op->m.as<P>();
+    a.l = op->l.as<P>();
+    a.x = op->x.as<P>();
+    a.s = op->s.as<P>();
+    a.xin = x;
+    a.out = y;
+    const mbr_ranker *r = op->rk;
+    if (r->kind == MBR_RANKER_TRIE) {
+        const TrieLevels &t = *r->trie;
+        a.trie.tab = t.table.as<uint32_t>();
+        a.trie.states = op->sec->states.p;
+        a.trie.ns = op->sec->n;
+        a.trie.M = t.M;
+        a.trie.H = t.H;
+        for (int lv = 0; lv < t.H; ++lv) {
+            a.trie.wmask[lv] = (uint32_t)((1ull << t.w[lv]) - 1);
+            a.trie.shift[lv] = t.shift[lv];
+            a.trie.off[lv] = t.off[lv];
+        }
+        a.trie.off[t.H] = t.off[t.H];
+        return launch_op<P, uint32_t, kTrie>(op, a, 0, st);
+    }
+    const StagTable &tb = r->stag;
+    a.stag.M = tb.M;
+    a.stag.k = tb.k;
+    a.stag.nch = tb.nch;
+    a.stag.N = r->N;
+    for (int c = 0; c < tb.nch && c < 16; ++c) a.stag.rowoff[c] = tb.rowoff[c];
+    a.stag.nentries = (uint64_t)tb.nrows << tb.k;
+    a.stab = tb.table.p;
+    const size_t lds = a.stag.nentries * tb.entry_bytes;
+    const bool in_lds = lds <= kLdsTable;
+    switch (tb.entry_bytes) {
+        case 2: return in_lds ? launch_op<P, uint16_t, kStagLds>(op, a, lds, st) : launch_op<P, uint16_t, kStagGlobal>(op, a, 0, st);
+        case 4: return in_lds ? launch_op<P, uint32_t, kStagLds>(op, a, lds, st) : launch_op<P, uint32_t, kStagGlobal>(op, a, 0, st);
+        default: return in_lds ? launch_op<P, uint64_t, kStagLds>(op, a, lds, st) : launch_op<P, uint64_t, kStagGlobal>(op, a, 0, st);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+mbr_status mbr_terms_from_hamiltonian(int32_t M, const double *t, int32_t n_u, const mbr_coulomb *u,
+                                      mbr_term *out, int64_t cap, int64_t *n_out) {
+    if (M < 1 || M > 64) MBR_FAIL(MBR_EINVAL, "M=%d outside 1..64", M);
+    if (n_u < 0 || (n_u > 0 && !u)) MBR_FAIL(MBR_EINVAL, "bad interaction list");
+    if (!n_out) MBR_FAIL(MBR_EINVAL, "null count pointer");
+    std::vector<Tup> ts;
+    if (t) {
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                const double a = t[(size_t)i * M + j];
+                if (a != 0.0) ts.push_back(product_of(-a, {creator(i), annihilator(j)}));
+            }
+    }
+    for (int q = 0; q < n_u; ++q) {
+        const mbr_coulomb &c = u[q];
+        if (c.i < 0 || c.j < 0 || c.k < 0 || c.l < 0 || c.i >= M || c.j >= M || c.k >= M || c.l >= M)
+            MBR_FAIL(MBR_EINVAL, "interaction %d has an orbital outside 0..M-1", q);
+        if (c.U != 0.0)
+            ts.push_back(product_of(0.25 * c.U, {creator(c.i), creator(c.j), annihilator(c.l), annihilator(c.k)}));
+    }
+    const std::vector<Tup> mt = merge_terms(std::move(ts));
+    *n_out = (int64_t)mt.size();
+    if (out && cap >= (int64_t)mt.size())
+        for (size_t i = 0; i < mt.size(); ++i) out[i] = mbr_term{mt[i].v, mt[i].m, mt[i].l, mt[i].r, mt[i].x, mt[i].s};
+    return MBR_OK;
+}
+
+mbr_status mbr_operator_create(const mbr_sector *sec, const mbr_ranker *rk, const mbr_term *terms,
+                               int64_t n_terms, mbr_operator **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!sec || !rk) MBR_FAIL(MBR_EINVAL, "null sector or ranker");
+    if (n_terms < 0 || (n_terms > 0 && !terms)) MBR_FAIL(MBR_EINVAL, "bad term list");
+    if (sec->n == 0) MBR_FAIL(MBR_EINVAL, "empty sector");
+    if (rk->kind == MBR_RANKER_TRIE) {
+        if (rk->sector != sec) MBR_FAIL(MBR_EINVAL, "the trie ranks a different sector");
+    } else if (rk->kind == MBR_RANKER_STAGGERED) {
+        // the sector must be exactly C^M_N of the table: one window with N set
+        // bits among all M orbitals and no other constraint
+        const uint64_t full = sec->M >= 64 ? ~0ull : ((1ull << sec->M) - 1);
+        const bool cnm = sec->modulus == 0 && sec->cons.size() == 1 && sec->cons[0].mask == full &&
+                         sec->cons[0].lo == rk->N && sec->cons[0].hi == rk->N;
+        if (rk->N < 0 || rk->M != sec->M || !cnm || rk->n_states != sec->n || rk->width_bits != sec->width_bits)
+            MBR_FAIL(MBR_EINVAL, "the staggered ranker does not rank this sector (C^M_N with one window)");
+    } else {
+        MBR_FAIL(MBR_EUNSUPPORTED, "operators rank with a staggered or trie ranker");
+    }
+    const uint64_t lim = sec->M >= 64 ? ~0ull : ((1ull << sec->M) - 1);
+    for (int64_t i = 0; i < n_terms; ++i) {
+        const mbr_term &t = terms[i];
+        if ((t.m | t.l | t.x | t.s) & ~lim) MBR_FAIL(MBR_EINVAL, "term %lld touches orbitals >= M", (long long)i);
+        if ((t.l & ~t.m) || (t.x & ~t.m)) MBR_FAIL(MBR_EINVAL, "term %lld: l and x must lie inside m", (long long)i);
+    }
+    auto op = std::make_unique<mbr_operator>();
+    op->sec = sec;
+    op->rk = rk;
+    op->nt = n_terms;
+    op->M = sec->M;
+    op->width_bits = sec->width_bits;
+    (void)hipGetDevice(&op->device);
+    const size_t n = (size_t)std::max<int64_t>(n_terms, 1);
+    std::vector<double> v(n, 0.0);
+    std::vector<uint64_t> f[4];
+    for (auto &a : f) a.assign(n, 0);
+    for (int64_t i = 0; i < n_terms; ++i) {
+        v[i] = terms[i].v;
+        f[0][i] = terms[i].m;
+        f[1][i] = terms[i].l;
+        f[2][i] = terms[i].x;
+        f[3][i] = terms[i].s;
+    }
+    hipStream_t st = as_stream(stream);
+    MBR_TRY(upload(op->v, v.data(), n * 8, st));
+    DevBuf *dst[4] = {&op->m, &op->l, &op->x, &op->s};
+    for (int k = 0; k < 4; ++k) {
+        if (sec->width_bits == 64) {
+            MBR_TRY(upload(*dst[k], f[k].data(), n * 8, st));
+        } else {
+            std::vector<uint32_t> w(f[k].begin(), f[k].end());
+            MBR_TRY(upload(*dst[k], w.data(), n * 4, st));
+        }
+    }
+    *out = op.release();
+    return MBR_OK;
+}
+
+mbr_status mbr_operator_apply(const mbr_operator *op, const double *d_x, double *d_y, void *stream) {
+    if (!op) MBR_FAIL(MBR_EINVAL, "null operator");
+    if (!d_x || !d_y) MBR_FAIL(MBR_EINVAL, "null vector");
+    if (d_x == d_y) MBR_FAIL(MBR_EINVAL, "x and y must not alias (gather form reads x while y is written)");
+    hipStream_t st = mbr::as_stream(stream);
+    if (op->width_bits == 32) return apply_t<uint32_t>(op, d_x, d_y, st);
+    return apply_t<uint64_t>(op, d_x, d_y, st);
+}
+
+mbr_status mbr_operator_destroy(mbr_operator *op) {
+    delete op;
+    return MBR_OK;
+}
+
+}  // extern "C"

@@ -24,17 +24,6 @@
 
 #include "common.hpp"
 
-struct TrieLevels {
-    int32_t M = 0, H = 0, width_bits = 32;
-    int32_t w[64] = {0};       // chunk widths, least significant first
-    int32_t shift[64] = {0};   // bit offset of chunk l in the pattern
-    uint64_t off[65] = {0};    // level l occupies entries off[l] .. off[l+1]-1
-    uint64_t entries = 0;
-    uint64_t lds_levels = 0;   // levels 0..lds_levels-1 are staged in LDS
-    uint64_t lds_entries = 0;
-    mbr::DevBuf table;         // uint32 entries of all levels
-};
-
 void trie_free(TrieLevels *t) { delete t; }
 uint64_t trie_bytes(const TrieLevels *t) { return t ? t->entries * 4 : 0; }
 int32_t trie_levels(const TrieLevels *t) { return t ? t->H : 0; }
