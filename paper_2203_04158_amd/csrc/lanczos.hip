@@ -208,14 +208,21 @@ __global__ void __launch_bounds__(kBlock) lz_scale_into(const HvTile *tiles, uin
 }
 
 // Reorthogonalising path: w = u - c3 v_j in place, then per-slot partials of
-// <v_k, w> for k = 0..j (classical Gram-Schmidt coefficients).
+// <v_k, w> for k = 0..j (classical Gram-Schmidt coefficients).  The basis
+// vectors are taken kKc at a time: one pass over the tile's rows reads kKc of
+// them (independent loads in flight) and one block reduction serves all kKc
+// sums.  Each sum is formed in the same order as a one-vector pass (per lane
+// in row order, then across the wave, then over the waves in order).
+constexpr int kKc = 8;
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, uint32_t n_tiles,
                                                          const HvSector *secs, T *__restrict__ W,
                                                          const T *__restrict__ V, uint64_t total,
                                                          int m, LzDev d) {
-    __shared__ double red[kRedWaves];
+    __shared__ double red[kKc][kRedWaves];
     const int j = *d.j;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const HvTile tl = tiles[ti];
         if (!d.active[tl.sector]) continue;
@@ -227,33 +234,49 @@ __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, ui
         const T *vj = V + (uint64_t)j * total;
         for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) W[base + e] = W[base + e] - c * vj[base + e];
         __syncthreads();
-        for (int k = 0; k <= j; ++k) {
-            const T *vk = V + (uint64_t)k * total;
-            double acc = 0;
-            for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
-                acc += (double)vk[base + e] * (double)W[base + e];
-            double s = block_sum(acc, red);
-            if (threadIdx.x == 0) pc[k] = s;
+        for (int k0 = 0; k0 <= j; k0 += kKc) {
+            const int nk = (j + 1 - k0) < kKc ? (j + 1 - k0) : kKc;
+            double acc[kKc];
+#pragma unroll
+            for (int q = 0; q < kKc; ++q) acc[q] = 0.0;
+            for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+                const double w = (double)W[base + e];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q)
+                    if (q < nk) acc[q] += (double)V[(uint64_t)(k0 + q) * total + base + e] * w;
+            }
+#pragma unroll
+            for (int q = 0; q < kKc; ++q) acc[q] = wave_sum(acc[q]);
+            __syncthreads();  // the previous chunk's readers of red are done
+            if (lane == 0)
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) red[q][wv] = acc[q];
+            __syncthreads();
+            if ((int)threadIdx.x < nk) {
+                double sum = 0;
+                for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) sum += red[threadIdx.x][w2];
+                pc[k0 + threadIdx.x] = sum;
+            }
         }
     }
 }
 
+// Per-sector Gram-Schmidt coefficients: lane k sums the slot partials of
+// <v_k, w> in slot order.
 __global__ void lz_reduce_cgs(const HvSector *secs, LzDev d, int m, uint32_t s_first) {
-    __shared__ double red[kRedWaves];
     const uint32_t s = s_first + blockIdx.x;
     if (!d.active[s]) return;
     const int j = *d.j;
     const HvSector sc = secs[s];
-    for (int k = 0; k <= j; ++k) {
+    for (int k = threadIdx.x; k <= j; k += blockDim.x) {
         double v = 0;
-        for (uint32_t i = threadIdx.x; i < sc.nslots; i += blockDim.x)
-            v += d.pc[(size_t)(sc.slot0 + i) * (m + 1) + k];
-        double t = block_sum(v, red);
-        if (threadIdx.x == 0) d.cgs[(size_t)s * (m + 1) + k] = t;
+        for (uint32_t i = 0; i < sc.nslots; ++i) v += d.pc[(size_t)(sc.slot0 + i) * (m + 1) + k];
+        d.cgs[(size_t)s * (m + 1) + k] = v;
     }
 }
 
-// w -= sum_k c_k v_k (fp64 accumulation), then partial |w|^2.
+// w -= sum_k c_k v_k (fp64 accumulation, k in order; the loads of kKc basis
+// vectors are issued together), then partial |w|^2.
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_subtract(const HvTile *tiles, uint32_t n_tiles,
                                                       const HvSector *secs, T *__restrict__ W,
@@ -274,7 +297,15 @@ __global__ void __launch_bounds__(kBlock) lz_subtract(const HvTile *tiles, uint3
         double acc = 0;
         for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
             double w = (double)W[base + e];
-            for (int k = 0; k <= j; ++k) w -= c[k] * (double)V[(uint64_t)k * total + base + e];
+            int k = 0;
+            for (; k + kKc <= j + 1; k += kKc) {
+                T v[kKc];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) v[q] = V[(uint64_t)(k + q) * total + base + e];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) w -= c[k + q] * (double)v[q];
+            }
+            for (; k <= j; ++k) w -= c[k] * (double)V[(uint64_t)k * total + base + e];
             T wt = (T)w;
             W[base + e] = wt;
             acc += (double)wt * (double)wt;
