@@ -350,6 +350,18 @@ def row_operator(torch, mbr, reps):
                              "trie_bytes": int(r.info().bytes)}
         del op, r
     res["exact"] = bool(torch.equal(ys[7], ys[14]))  # two trie layouts, identical sums
+    # ground state of the K = 0 sector by the operator's fp64 Lanczos; the
+    # real-space chain's E0 (stored oracle value) is the minimum over K
+    r = mbr.build_trie(sec, 14)
+    op = mbr.operator_create(sec, r, terms)
+    v0 = torch.from_numpy(synth.start_vector(7, sec.size)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, nst, _, _ = mbr.operator_lanczos(op, v0, 200)
+    dt = time.perf_counter() - t0
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "hubbard_chain_L14.json")))["e0_exact"]
+    res["lanczos"] = {"steps": nst, "value": nst / dt, "unit": "Lanczos steps/s", "e0_K0": e0,
+                      "e0_real_space_oracle": gold, "rel_diff": abs(e0 - gold) / abs(gold)}
     return res
 
 

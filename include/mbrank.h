@@ -298,6 +298,18 @@ mbr_status mbr_operator_create(const mbr_sector *s, const mbr_ranker *r, const m
  * not alias). */
 mbr_status mbr_operator_apply(const mbr_operator *op, const double *d_x, double *d_y, void *stream);
 
+/* Lowest eigenvalue of the operator on its sector by plain fp64 Lanczos
+ * (three vectors, no reorthogonalisation; the minimum is unaffected by ghost
+ * copies): alpha_j = <v_j, H v_j>, w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1},
+ * beta_j = |w|, v_{j+1} = w / beta_j, from v_0 = d_v0 / |d_v0| (fp64, the
+ * sector's size), for nsteps steps, as many steps as the sector has states,
+ * or until beta_j <= tol (|alpha_j| + beta_{j-1}); then the lowest eigenvalue of the tridiagonal matrix (Sturm
+ * bisection, as mbr_tridiag_lowest).  Host outputs: *e0, *steps_done, and the
+ * coefficients alpha[0..nsteps), beta[0..nsteps) when not NULL.  Allocates
+ * three work vectors; synchronises `stream`. */
+mbr_status mbr_operator_lanczos(const mbr_operator *op, const double *d_v0, int32_t nsteps, double tol,
+                                double *e0, int32_t *steps_done, double *alpha, double *beta, void *stream);
+
 mbr_status mbr_operator_destroy(mbr_operator *op);
 
 /* ======================================================================== */

@@ -115,6 +115,8 @@ _SIGS = {
                                         C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_operator_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_operator_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_operator_lanczos": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_rank_batch64": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_build_bisect_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
@@ -450,6 +452,18 @@ def operator_create(sector: Sector, ranker: Ranker, terms, stream=None) -> Opera
 def operator_apply(op: Operator, x, y, stream=None):
     _check("mbr_operator_apply", lib().mbr_operator_apply(op.handle, _dptr(x), _dptr(y), _stream(stream)))
     return y
+
+
+def operator_lanczos(op: Operator, v0, nsteps: int, tol: float = 1e-12, stream=None):
+    """(E0, steps taken, alpha[nsteps], beta[nsteps]) by fp64 Lanczos on the GPU."""
+    e0 = C.c_double()
+    nd = C.c_int32()
+    al = np.zeros(nsteps)
+    be = np.zeros(nsteps)
+    _check("mbr_operator_lanczos", lib().mbr_operator_lanczos(op.handle, _dptr(v0), nsteps, tol, C.byref(e0),
+                                                              C.byref(nd), C.c_void_p(al.ctypes.data),
+                                                              C.c_void_p(be.ctypes.data), _stream(stream)))
+    return float(e0.value), int(nd.value), al, be
 
 
 # --------------------------------------------------------------------------- Hamiltonian

@@ -148,6 +148,102 @@ __global__ void __launch_bounds__(kBlock) op_apply_kernel(OpArgs<P> a) {
     }
 }
 
+// ---------------------------------------------------------------- Lanczos
+// Plain fp64 Lanczos on an operator (three vectors, no reorthogonalisation):
+// alpha_j = <v_j, H v_j>; w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1};
+// beta_j = |w|; v_{j+1} = w / beta_j.  Dot products are fixed-order two-level
+// reductions (kRedBlocks block partials, then one block), so runs repeat
+// bitwise.  The recurrence stops (the remaining kernels do nothing) once
+// beta_j <= tol (|alpha_j| + beta_{j-1}) or after as many steps as the sector
+// has states; *len holds the steps taken.
+constexpr unsigned kRedBlocks = 1024;
+
+__device__ __forceinline__ double blk_sum(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+__global__ void op_start_kernel(int32_t *len, int32_t nsteps) { *len = nsteps; }
+
+__global__ void __launch_bounds__(kBlock) op_dot_parts(const double *__restrict__ a, const double *__restrict__ b,
+                                                       uint64_t n, double *parts) {
+    __shared__ double red[kBlock / 64];
+    double acc = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        acc = __builtin_fma(a[i], b[i], acc);
+    const double s = blk_sum(acc, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+// out = sum of the kRedBlocks partials (sqrt of it when root != 0).
+__global__ void __launch_bounds__(kBlock) op_reduce(const double *parts, double *out, int root) {
+    __shared__ double red[kBlock / 64];
+    double acc = 0;
+    for (unsigned i = threadIdx.x; i < kRedBlocks; i += blockDim.x) acc += parts[i];
+    const double s = blk_sum(acc, red);
+    if (threadIdx.x == 0) *out = root ? sqrt(s) : s;
+}
+
+__global__ void __launch_bounds__(kBlock) op_scale_kernel(const double *__restrict__ v0, double *__restrict__ v,
+                                                          double *__restrict__ vp, uint64_t n, const double *norm) {
+    const double c = *norm > 0 ? 1.0 / *norm : 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        v[i] = v0[i] * c;
+        vp[i] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) op_update_kernel(double *__restrict__ w, const double *__restrict__ v,
+                                                           const double *__restrict__ vp, uint64_t n,
+                                                           const double *al, const double *be, int j,
+                                                           const int32_t *len, double *parts) {
+    __shared__ double red[kBlock / 64];
+    if (j >= *len) return;
+    const double a = al[j], b = j > 0 ? be[j - 1] : 0.0;
+    double acc = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double x = w[i] - a * v[i] - b * vp[i];
+        w[i] = x;
+        acc = __builtin_fma(x, x, acc);
+    }
+    const double s = blk_sum(acc, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) op_beta_kernel(const double *parts, const double *al, double *be, int j,
+                                                         int nsteps, uint64_t dim, double tol, int32_t *len) {
+    __shared__ double red[kBlock / 64];
+    if (j >= *len) return;
+    double acc = 0;
+    for (unsigned i = threadIdx.x; i < kRedBlocks; i += blockDim.x) acc += parts[i];
+    const double s = blk_sum(acc, red);
+    if (threadIdx.x == 0) {
+        const double b = sqrt(s);
+        const double bprev = j > 0 ? be[j - 1] : 0.0;
+        // the Krylov space cannot outgrow the sector
+        const bool stop = b <= tol * (fabs(al[j]) + bprev) || j + 1 >= nsteps || (uint64_t)(j + 1) >= dim;
+        be[j] = stop ? 0.0 : b;
+        if (stop) *len = j + 1;
+    }
+}
+
+// v_{j+1} = w / beta_j, in place in w's buffer (the caller rotates the buffers).
+__global__ void __launch_bounds__(kBlock) op_next_kernel(double *__restrict__ w, const double *__restrict__ v,
+                                                         const double *__restrict__ vp, uint64_t n,
+                                                         const double *be, int j, const int32_t *len) {
+    if (j + 1 >= *len) return;
+    const double c = 1.0 / be[j];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        w[i] *= c;
+}
+
 }  // namespace
 
 struct mbr_operator {
@@ -317,6 +413,55 @@ mbr_status mbr_operator_apply(const mbr_operator *op, const double *d_x, double 
     hipStream_t st = mbr::as_stream(stream);
     if (op->width_bits == 32) return apply_t<uint32_t>(op, d_x, d_y, st);
     return apply_t<uint64_t>(op, d_x, d_y, st);
+}
+
+mbr_status mbr_operator_lanczos(const mbr_operator *op, const double *d_v0, int32_t nsteps, double tol,
+                                double *e0, int32_t *steps_done, double *alpha, double *beta, void *stream) {
+    using namespace mbr;
+    if (!op || !d_v0) MBR_FAIL(MBR_EINVAL, "null operator or start vector");
+    if (nsteps < 1 || nsteps > 100000) MBR_FAIL(MBR_EINVAL, "nsteps=%d", nsteps);
+    if (!(tol >= 0.0)) MBR_FAIL(MBR_EINVAL, "tolerance must be non-negative");
+    hipStream_t st = as_stream(stream);
+    const uint64_t n = op->sec->n;
+    DevBuf buf[3], parts, sc, d_len, d_e0;
+    for (auto &b2 : buf) MBR_TRY(b2.alloc(n * 8));
+    MBR_TRY(parts.alloc(kRedBlocks * 8));
+    MBR_TRY(sc.alloc((2 * (size_t)nsteps + 2) * 8));
+    MBR_TRY(d_len.alloc(4));
+    MBR_TRY(d_e0.alloc(8));
+    double *al = sc.as<double>(), *be = al + nsteps, *norm = be + nsteps;
+    int32_t *len = d_len.as<int32_t>();
+    // v_0 = v0 / |v0|; the previous vector starts at zero
+    double *vp = buf[0].as<double>(), *v = buf[1].as<double>(), *w = buf[2].as<double>();
+    op_start_kernel<<<1, 1, 0, st>>>(len, nsteps);
+    op_dot_parts<<<kRedBlocks, kBlock, 0, st>>>(d_v0, d_v0, n, parts.as<double>());
+    op_reduce<<<1, kBlock, 0, st>>>(parts.as<double>(), norm, 1);
+    op_scale_kernel<<<kRedBlocks, kBlock, 0, st>>>(d_v0, v, vp, n, norm);
+    MBR_HIP(hipGetLastError());
+    for (int32_t j = 0; j < nsteps; ++j) {
+        MBR_TRY(mbr_operator_apply(op, v, w, stream));  // w = H v_j
+        op_dot_parts<<<kRedBlocks, kBlock, 0, st>>>(v, w, n, parts.as<double>());
+        op_reduce<<<1, kBlock, 0, st>>>(parts.as<double>(), al + j, 0);
+        op_update_kernel<<<kRedBlocks, kBlock, 0, st>>>(w, v, vp, n, al, be, j, len, parts.as<double>());
+        op_beta_kernel<<<1, kBlock, 0, st>>>(parts.as<double>(), al, be, j, nsteps, n, tol, len);
+        op_next_kernel<<<kRedBlocks, kBlock, 0, st>>>(w, v, vp, n, be, j, len);
+        MBR_HIP(hipGetLastError());
+        double *t = vp;  // v_{j+1} now sits in w's buffer, v_j becomes the previous vector
+        vp = v;
+        v = w;
+        w = t;
+    }
+    MBR_TRY(mbr_tridiag_lowest(al, be, len, nsteps, 1, d_e0.as<double>(), stream));
+    int32_t hl = 0;
+    double he = 0;
+    MBR_HIP(hipMemcpyAsync(&hl, len, 4, hipMemcpyDeviceToHost, st));
+    MBR_HIP(hipMemcpyAsync(&he, d_e0.p, 8, hipMemcpyDeviceToHost, st));
+    if (alpha) MBR_HIP(hipMemcpyAsync(alpha, al, (size_t)nsteps * 8, hipMemcpyDeviceToHost, st));
+    if (beta) MBR_HIP(hipMemcpyAsync(beta, be, (size_t)nsteps * 8, hipMemcpyDeviceToHost, st));
+    MBR_HIP(hipStreamSynchronize(st));
+    if (e0) *e0 = he;
+    if (steps_done) *steps_done = hl;
+    return MBR_OK;
 }
 
 mbr_status mbr_operator_destroy(mbr_operator *op) {

@@ -156,3 +156,39 @@ def test_operator_rejects_bad_input():
     x = torch.zeros(sec.size, dtype=torch.float64, device="cuda")
     with pytest.raises(mbr.MbrError):
         mbr.operator_apply(op, x, x)                                          # aliasing
+
+
+def test_operator_lanczos_momentum_and_particle_sectors():
+    """E0 by the operator's GPU Lanczos: every total-momentum sector of the
+    L = 6 ring against dense diagonalisation of the oracle's matrix, their
+    minimum against the real-space E0, and a random Eq. H on C^12_5."""
+    L, nu, nd, U = 6, 3, 3, 4.0
+    M, t, cl = _ring_momentum(L, U)
+    terms = mbr.terms_from_hamiltonian(M, t, cl)
+    otl = _oracle_terms(M, t, cl)
+    lows = []
+    for K in range(L):
+        cons, w, st = _momentum_sector(L, nu, nd, K)
+        sec = mbr.sector_build_mod(M, cons, w, L, K)
+        op = mbr.operator_create(sec, mbr.build_trie(sec, 6), terms)
+        v0 = torch.from_numpy(synth.start_vector(K + 1, sec.size)).cuda()
+        e0, nst, _, _ = mbr.operator_lanczos(op, v0, 120)
+        want = np.linalg.eigvalsh(OH.dense(st, otl))[0]
+        assert nst <= sec.size
+        assert abs(e0 - want) <= 1e-9 * max(1.0, abs(want)), (K, e0, want, nst)
+        lows.append(e0)
+    assert abs(min(lows) - (-3.668706178873)) < 1e-9
+    M, N = 12, 5
+    st = OC.sector_enumerate(M, OC.constraints(M, N))
+    sec = mbr.sector_build(M, OC.constraints(M, N))
+    t, cl = _random_nconserving(M, 77, 30)
+    cl = cl + [(k, l, i, j, U) for i, j, k, l, U in cl]   # add the Hermitian conjugates
+    op = mbr.operator_create(sec, mbr.build_staggered_tables(M, N, 6), mbr.terms_from_hamiltonian(M, t, cl))
+    e0, nst, a, b = mbr.operator_lanczos(op, torch.from_numpy(synth.start_vector(9, sec.size)).cuda(), 300)
+    Hd = OH.dense(st, _oracle_terms(M, t, cl))
+    assert np.abs(Hd - Hd.T).max() <= 1e-12
+    want = np.linalg.eigvalsh(Hd)[0]
+    assert abs(e0 - want) <= 1e-9 * max(1.0, abs(want)), (e0, want, nst)
+    # the same run twice gives bitwise the same coefficients
+    e1, nst1, a1, b1 = mbr.operator_lanczos(op, torch.from_numpy(synth.start_vector(9, sec.size)).cuda(), 300)
+    assert e1 == e0 and nst1 == nst and np.array_equal(a[:nst], a1[:nst]) and np.array_equal(b[:nst], b1[:nst])
