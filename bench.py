@@ -163,7 +163,7 @@ def row_staggered(torch, mbr, reps):
     ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
     exact = bool(torch.equal(out, idx))
     roof = hbm_roofline(8.0 * nq, ms, "rank_staggered_kernel (4 B in, 4 B out per query)")
-    roof["traffic"] = traffic_for("rank_staggered_kernel<unsignedint,unsignedint,true,4>")
+    roof["traffic"] = traffic_for("rank_staggered_kernel<unsignedint,unsignedint,true,4,unsignedint>")
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
             "roofline": roof}
@@ -496,6 +496,12 @@ def main():
     alg_bytes = 16.0 * dim  # x read once + y written once, fp64
     roof = hbm_roofline(alg_bytes, hv_ms, "hv_rows_kernel (plain H·x)")
     roof["traffic"] = traffic_for("hv_rows_kernel<double,false,4,true>") if launch_cfg["G"] == 0 else None
+    # context: with the up-hop gathers counted (8 B per hop changing alpha_up;
+    # down-hop sources come from the row staged in LDS) the bytes that must
+    # cross L2 per product
+    up_hops = L * 2 * math.comb(L - 2, NUP - 1) * math.comb(L, NDN)
+    roof["alg_bytes_with_up_gathers"] = alg_bytes + 8.0 * up_hops
+    roof["achieved_with_up_gathers"] = roof["alg_bytes_with_up_gathers"] / (hv_ms * 1e-3) / 1e9
 
     steps = args.steps
     ms_per_step = elapsed * 1e3 / steps
