@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(kBlock) lz_scale_into(const HvTile *tiles, uin
 // sums.  Each sum is formed in the same order as a one-vector pass (per lane
 // in row order, then across the wave, then over the waves in order).
 constexpr int kKc = 8;
+constexpr uint64_t kGroupRows = 4096;  // rows per merged group of the Gram-Schmidt kernels
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, uint32_t n_tiles,
@@ -385,6 +386,12 @@ struct mbr_lanczos {
     uint32_t n_slots = 0;
     std::vector<HvSector> secs;
     DevBuf d_tiles_slot, d_secs;
+    // reorthogonalising path: consecutive tiles of a sector merged into groups
+    // of at least kGroupRows rows, with their own slot numbering (rsecs holds
+    // the sectors with slot0/nslots over those slots); rt0/rnt per sector
+    DevBuf d_rtiles, d_rsecs;
+    std::vector<uint32_t> rt0, rnt;
+    uint32_t n_rtiles = 0;
     DevBuf bufA, bufB, basis, work;
     DevBuf alpha, beta, c1, c2, c3, pd, pn, pc, cgs, norm0, active, steps, jcount, e0;
     LzDev dev{};
@@ -458,13 +465,20 @@ mbr_status enqueue_reorth(mbr_lanczos *lz, uint32_t s0, uint32_t nsec, uint32_t 
         ep.sector = s0;
     }
     MBR_TRY(hubbard_launch(lz->h, V, W, ep, s));
-    const unsigned g = std::min<unsigned>(lz->grid, nt);
+    // the Gram-Schmidt kernels run over the merged groups of these sectors
+    const uint32_t g0 = all ? 0 : lz->rt0[s0], gn = all ? lz->n_rtiles : lz->rnt[s0];
+    const HvTile *groups = lz->d_rtiles.as<HvTile>() + g0;
+    const HvSector *rsecs = lz->d_rsecs.as<HvSector>();
+    // batched: one workgroup per group, so the dispatcher balances groups of
+    // unequal size; per sector: the tile grid of the other kernels
+    const unsigned g = all ? std::max<unsigned>(1, std::min<unsigned>(gn, 1u << 20))
+                           : std::min<unsigned>(lz->grid, gn);
     lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
-    lz_update_dots<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->m, lz->dev);
-    lz_reduce_cgs<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
-    lz_subtract<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->m, lz->dev);
-    lz_beta<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, default_tol(lz), 1, s0);
-    lz_scale_into<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, W, V, lz->total, lz->dev, 1);
+    lz_update_dots<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->m, lz->dev);
+    lz_reduce_cgs<<<nsec, kBlock, 0, s>>>(rsecs, lz->dev, lz->m, s0);
+    lz_subtract<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->m, lz->dev);
+    lz_beta<<<nsec, kBlock, 0, s>>>(rsecs, lz->dev, lz->m, default_tol(lz), 1, s0);
+    lz_scale_into<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->dev, 1);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
@@ -554,6 +568,38 @@ mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o, m
     hipStream_t s = nullptr;
     MBR_TRY(upload(lz->d_tiles_slot, tiles.data(), tiles.size() * sizeof(HvTile), s));
     MBR_TRY(upload(lz->d_secs, lz->secs.data(), lz->secs.size() * sizeof(HvSector), s));
+    if (o->reorth) {
+        // batched steps: merge a sector's tiles (contiguous rows, slot order)
+        // into groups of at least kGroupRows rows, so there is one block
+        // reduction per group and basis vector instead of one per tile.
+        // Per-sector launches keep the tiles (a lone sector needs them all to
+        // fill the GPU).
+        const uint64_t grow = o->batched ? kGroupRows : 0;
+        std::vector<HvTile> groups;
+        std::vector<HvSector> rsecs = lz->secs;
+        lz->rt0.assign(lz->ns, 0);
+        lz->rnt.assign(lz->ns, 0);
+        for (int si = 0; si < lz->ns; ++si) {
+            const HvSector &sc = lz->secs[si];
+            lz->rt0[si] = (uint32_t)groups.size();
+            rsecs[si].slot0 = (uint32_t)groups.size();
+            for (uint32_t t = sc.slot0; t < sc.slot0 + sc.nslots;) {
+                HvTile g = tiles[t];
+                g.slot = (uint32_t)groups.size();
+                uint64_t rows = (uint64_t)g.nblk * sc.cdn;
+                for (++t; t < sc.slot0 + sc.nslots && rows < grow; ++t) {
+                    g.nblk += tiles[t].nblk;  // tiles[t] starts where the group ends
+                    rows += (uint64_t)tiles[t].nblk * sc.cdn;
+                }
+                groups.push_back(g);
+            }
+            lz->rnt[si] = (uint32_t)groups.size() - lz->rt0[si];
+            rsecs[si].nslots = lz->rnt[si];
+        }
+        lz->n_rtiles = (uint32_t)groups.size();
+        MBR_TRY(upload(lz->d_rtiles, groups.data(), groups.size() * sizeof(HvTile), s));
+        MBR_TRY(upload(lz->d_rsecs, rsecs.data(), rsecs.size() * sizeof(HvSector), s));
+    }
     const size_t ns = lz->ns, m = lz->m, nsl = lz->n_slots;
     if (o->reorth) {
         const double bytes = (double)lz->total * lz->tsz * (m + 2);
