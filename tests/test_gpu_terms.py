@@ -192,3 +192,33 @@ def test_operator_lanczos_momentum_and_particle_sectors():
     # the same run twice gives bitwise the same coefficients
     e1, nst1, a1, b1 = mbr.operator_lanczos(op, torch.from_numpy(synth.start_vector(9, sec.size)).cuda(), 300)
     assert e1 == e0 and nst1 == nst and np.array_equal(a[:nst], a1[:nst]) and np.array_equal(b[:nst], b1[:nst])
+
+
+def test_operator_momentum_ring_l14_full_size_sampled():
+    """The benchmark workload: L = 14, (7,7), total momentum 0 (841,332 states,
+    2,772 tuples), k = 14 trie; sampled rows (first, last, and seeded) against
+    the oracle's tuple apply, and an empty term list gives zero."""
+    L, K = 14, 0
+    M, t, cl = _ring_momentum(L, 4.0)
+    cons = OC.spin_constraints(L, 7, 7)
+    st = OH.sector(L, 7, 7)
+    w = np.array([k for k in range(L)] * 2, dtype=np.int64)
+    mom = np.zeros(st.size, dtype=np.int64)
+    for i in range(M):
+        mom += ((st >> np.uint64(i)) & np.uint64(1)).astype(np.int64) * w[i]
+    st = st[mom % L == K]
+    sec = mbr.sector_build_mod(M, cons, list(w), L, K)
+    assert sec.size == st.size == 841332
+    terms = mbr.terms_from_hamiltonian(M, t, cl)
+    assert len(terms) == 2772
+    op = mbr.operator_create(sec, mbr.build_trie(sec, 14), terms)
+    x = 2 * synth.uniform01(21, st.size) - 1
+    y = torch.empty(st.size, dtype=torch.float64, device="cuda")
+    mbr.operator_apply(op, torch.from_numpy(x).cuda(), y)
+    rows = np.unique(np.concatenate([[0, st.size - 1], synth.uniform_indices(22, 1500, st.size)]))
+    want, ab = OH.apply(st, _oracle_terms(M, t, cl), x, rows=rows, with_abssum=True)
+    got = y.cpu().numpy()[rows]
+    assert (np.abs(got - want) <= 64 * EPS64 * ab + 1e-300).all()
+    empty = mbr.operator_create(sec, mbr.build_trie(sec, 14), [])
+    mbr.operator_apply(empty, torch.from_numpy(x).cuda(), y)
+    assert not torch.any(y != 0)
