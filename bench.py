@@ -434,8 +434,10 @@ def main():
                          "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the path is built and measured on a single "
-              "MI355X (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the path is built and measured on a single MI355X "
+              "(across GPUs, ranking would split the queries, a large sector its alpha_up blocks "
+              "with one x exchange per H·x, and the batched impurity model whole sectors)",
+              file=sys.stderr)
         sys.exit(2)
     rows = [] if args.rows == "none" else (list(ROWS) if args.rows == "all" else args.rows.split(","))
     for r in rows:

@@ -49,7 +49,7 @@ typedef int32_t mbr_status;
 #define MBR_ENOTSORTED   (-4) /* caller-supplied state list not strictly ascending */
 #define MBR_EDUP         (-5) /* caller-supplied state list has a repeated entry */
 #define MBR_ERANGE       (-6) /* an index or size exceeds what the handle supports */
-#define MBR_EUNSUPPORTED (-7) /* valid request this build does not implement */
+#define MBR_EUNSUPPORTED (-7) /* valid request the library does not implement */
 
 #define MBR_NOT_FOUND 0xFFFFFFFFu
 
