@@ -33,6 +33,27 @@ __device__ __forceinline__ uint64_t stag_rank(P x, const E *tab, const StagArgs 
     return rank;
 }
 
+// Copy `bytes` from global memory to LDS with 16-byte accesses (both
+// addresses 16-byte aligned), four in flight per lane before the first store,
+// then the tail by 4-byte words (bytes is a multiple of 4).  No barrier.
+__device__ __forceinline__ void stage_to_lds(void *lds, const void *__restrict__ g, uint64_t bytes) {
+    const uint4 *src = static_cast<const uint4 *>(g);
+    uint4 *dst = static_cast<uint4 *>(lds);
+    const uint64_t n16 = bytes >> 4;
+    uint64_t i = threadIdx.x;
+    for (; i + 3 * blockDim.x < n16; i += 4 * blockDim.x) {
+        const uint4 v0 = src[i], v1 = src[i + blockDim.x], v2 = src[i + 2 * blockDim.x], v3 = src[i + 3 * blockDim.x];
+        dst[i] = v0;
+        dst[i + blockDim.x] = v1;
+        dst[i + 2 * blockDim.x] = v2;
+        dst[i + 3 * blockDim.x] = v3;
+    }
+    for (; i < n16; i += blockDim.x) dst[i] = src[i];
+    const uint32_t *s4 = static_cast<const uint32_t *>(g);
+    uint32_t *d4 = static_cast<uint32_t *>(lds);
+    for (uint64_t k = (n16 << 2) + threadIdx.x; k < (bytes >> 2); k += blockDim.x) d4[k] = s4[k];
+}
+
 // A trie in the level-major layout of trie.hip, read from global memory.
 struct TrieWalk {
     const uint32_t *tab;

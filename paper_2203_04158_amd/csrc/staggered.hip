@@ -78,9 +78,15 @@ int entry_bytes_for(int M, int nmax) {
 
 constexpr unsigned kBlock = 256;
 
+// The whole table into LDS (16-byte copies; the table's byte size is a
+// multiple of 4: 2^k entries per row, k >= 1, entries of 2 bytes or more).
 template <class E>
 __device__ __forceinline__ void load_table(E *lds, const E *__restrict__ g, uint64_t n) {
-    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+    if ((n * sizeof(E)) % 4 == 0) {
+        stage_to_lds(lds, g, n * sizeof(E));
+    } else {
+        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+    }
     __syncthreads();
 }
 

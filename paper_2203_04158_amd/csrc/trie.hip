@@ -22,7 +22,7 @@
 #include <cstring>
 #include <memory>
 
-#include "common.hpp"
+#include "rank_device.hpp"
 
 void trie_free(TrieLevels *t) { delete t; }
 uint64_t trie_bytes(const TrieLevels *t) { return t ? t->entries * 4 : 0; }
@@ -55,7 +55,7 @@ template <class P>
 __global__ void __launch_bounds__(kBlock) trie_rank_kernel(const P *__restrict__ q, uint64_t n,
                                                            uint32_t *__restrict__ out, TrieArgs a) {
     extern __shared__ __align__(16) uint32_t top[];
-    for (uint32_t i = threadIdx.x; i < a.lds_entries; i += blockDim.x) top[i] = a.tab[i];
+    stage_to_lds(top, a.tab, (uint64_t)a.lds_entries * 4);
     __syncthreads();
     const P *states = static_cast<const P *>(a.states);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
