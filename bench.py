@@ -261,6 +261,24 @@ def row_learned(torch, mbr, reps, big: bool):
         train_s = time.perf_counter() - t0
         res["learned_train_s"] = train_s
         res["learned_stats"] = mbr.learned_stats(lr_)
+        if name == cases[0][0]:
+            # stage 1 alone on the matrix cores: the network's forward pass over
+            # the 2^24 queries (the entry point also rounds the parameters to
+            # bf16 into two small scratch buffers and synchronises)
+            params = torch.from_numpy(mbr.learned_params(lr_)).cuda()
+            yq = torch.empty(nq, dtype=torch.float32, device="cuda")
+            mbr.mlp_forward(params, q, out=yq)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                mbr.mlp_forward(params, q, out=yq)
+            torch.cuda.synchronize()
+            mlp_ms = (time.perf_counter() - t0) * 1e3 / 5
+            flops = 12416.0 * nq
+            res["mlp_forward"] = {"ms": mlp_ms, "roofline": {
+                "bound": "mfma", "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": 2500.0,
+                "unit": "TFLOP/s", "frac": flops / (mlp_ms * 1e-3) / 1e12 / 2500.0,
+                "kernel": "mlp_forward_kernel (12,416 flop per query, bf16 MFMA, fp32 accumulation)"}}
         res["learned_train"] = ("8 epochs x min(N_s, 2^22) samples, batch 4096, Adam lr 2e-3, seed 4; "
                                 "2^b leaves, about 4 members per leaf")
         rankers = [("trie_k8", trie), ("learned", lr_)]
