@@ -164,9 +164,18 @@ def row_staggered(torch, mbr, reps):
     exact = bool(torch.equal(out, idx))
     roof = hbm_roofline(8.0 * nq, ms, "rank_staggered_kernel (4 B in, 4 B out per query)")
     roof["traffic"] = traffic_for("rank_staggered_kernel<unsignedint,unsignedint,true,4,unsignedint>")
+    # steady state: 2^28 queries (the 2^22 above, 64 times over; 2 GB moved
+    # per launch, far beyond the caches)
+    big_q = q.repeat(64)
+    big_out = torch.empty(big_q.numel(), dtype=torch.int32, device="cuda")
+    ms_big = time_launches(torch, lambda: mbr.rank_batch(r, big_q, out=big_out), 5)
+    stress = {"queries": big_q.numel(), "kernel_ms": ms_big, "value": big_q.numel() / (ms_big * 1e-3) / 1e9,
+              "exact": bool(torch.equal(big_out, idx.repeat(64))),
+              "roofline": hbm_roofline(8.0 * big_q.numel(), ms_big, "rank_staggered_kernel, 2^28 queries")}
+    del big_q, big_out
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
-            "roofline": roof}
+            "roofline": roof, "stress_2e28": stress}
 
 
 def row_staggered64(torch, mbr, reps):
