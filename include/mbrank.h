@@ -305,7 +305,8 @@ mbr_status mbr_operator_apply(const mbr_operator *op, const double *d_x, double 
  * sector's size), for nsteps steps, as many steps as the sector has states,
  * or until beta_j <= tol (|alpha_j| + beta_{j-1}); then the lowest eigenvalue of the tridiagonal matrix (Sturm
  * bisection, as mbr_tridiag_lowest).  Host outputs: *e0, *steps_done, and the
- * coefficients alpha[0..nsteps), beta[0..nsteps) when not NULL.  Allocates
+ * coefficients alpha[0..nsteps), beta[0..nsteps) when not NULL (entries from
+ * steps_done on are zero).  Allocates
  * three work vectors; synchronises `stream`. */
 mbr_status mbr_operator_lanczos(const mbr_operator *op, const double *d_v0, int32_t nsteps, double tol,
                                 double *e0, int32_t *steps_done, double *alpha, double *beta, void *stream);

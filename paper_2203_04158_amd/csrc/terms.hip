@@ -235,11 +235,12 @@ __global__ void __launch_bounds__(kBlock) op_beta_kernel(const double *parts, co
 }
 
 // v_{j+1} = w / beta_j, in place in w's buffer (the caller rotates the buffers).
+// Once the recurrence has stopped the buffer is zeroed instead, so the steps
+// the host still enqueues work on zero vectors (alpha = 0, nothing grows).
 __global__ void __launch_bounds__(kBlock) op_next_kernel(double *__restrict__ w, const double *__restrict__ v,
                                                          const double *__restrict__ vp, uint64_t n,
                                                          const double *be, int j, const int32_t *len) {
-    if (j + 1 >= *len) return;
-    const double c = 1.0 / be[j];
+    const double c = (j + 1 >= *len) ? 0.0 : 1.0 / be[j];
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         w[i] *= c;
 }
@@ -430,6 +431,7 @@ mbr_status mbr_operator_lanczos(const mbr_operator *op, const double *d_v0, int3
     MBR_TRY(d_len.alloc(4));
     MBR_TRY(d_e0.alloc(8));
     double *al = sc.as<double>(), *be = al + nsteps, *norm = be + nsteps;
+    MBR_HIP(hipMemsetAsync(sc.p, 0, (2 * (size_t)nsteps + 2) * 8, st));
     int32_t *len = d_len.as<int32_t>();
     // v_0 = v0 / |v0|; the previous vector starts at zero
     double *vp = buf[0].as<double>(), *v = buf[1].as<double>(), *w = buf[2].as<double>();

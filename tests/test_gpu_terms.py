@@ -192,6 +192,17 @@ def test_operator_lanczos_momentum_and_particle_sectors():
     # the same run twice gives bitwise the same coefficients
     e1, nst1, a1, b1 = mbr.operator_lanczos(op, torch.from_numpy(synth.start_vector(9, sec.size)).cuda(), 300)
     assert e1 == e0 and nst1 == nst and np.array_equal(a[:nst], a1[:nst]) and np.array_equal(b[:nst], b1[:nst])
+    # a sector smaller than the step count: the recurrence stops at its size
+    # and the coefficients past the stop are zero
+    sec = mbr.sector_build(6, OC.constraints(6, 2))
+    op = mbr.operator_create(sec, mbr.build_staggered_tables(6, 2, 3),
+                             mbr.terms_from_hamiltonian(6, np.eye(6) + 0.3 * np.ones((6, 6)), []))
+    e2, n2, a2, b2 = mbr.operator_lanczos(op, torch.from_numpy(synth.start_vector(3, sec.size)).cuda(), 50)
+    assert n2 <= sec.size and not a2[n2:].any() and not b2[n2 - 1:].any()
+    st = OC.sector_enumerate(6, OC.constraints(6, 2))
+    t6 = np.eye(6) + 0.3 * np.ones((6, 6))
+    want = np.linalg.eigvalsh(OH.dense(st, _oracle_terms(6, t6, [])))[0]
+    assert abs(e2 - want) <= 1e-10 * max(1.0, abs(want))
 
 
 def test_operator_momentum_ring_l14_full_size_sampled():
