@@ -98,7 +98,7 @@ const char *mbr_status_str(mbr_status s) {
 
 const char *mbr_last_error(void) { return mbr::g_err.c_str(); }
 
-int32_t mbr_version(void) { return 10000; }
+int32_t mbr_version(void) { return 10100; }
 
 mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info) {
     if (!r || !info) MBR_FAIL(MBR_EINVAL, "null ranker or info");

@@ -60,10 +60,19 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
-// Sum of n partials of one sector by one workgroup, fixed order.
+// Sum of n partials of one sector by one workgroup, fixed order (lane t adds
+// p[t], p[t + B], ... in turn; eight loads are issued before they are added).
 __device__ __forceinline__ double sector_sum(const double *p, uint32_t n, double *red) {
     double v = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    uint32_t i = threadIdx.x;
+    for (; i + 7 * blockDim.x < n; i += 8 * blockDim.x) {
+        double t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = p[i + q * blockDim.x];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v += t[q];
+    }
+    for (; i < n; i += blockDim.x) v += p[i];
     return block_sum(v, red);
 }
 
@@ -134,6 +143,49 @@ __global__ void __launch_bounds__(kBlock) lz_update(const HvTile *tiles, uint32_
         }
         double s = block_sum(acc, red);
         if (threadIdx.x == 0) d.pn[tl.slot] = s;
+    }
+}
+
+// One sector per launch: lz_alpha folded into lz_update.  Every workgroup
+// forms alpha_j from the sector's partials itself (the same sum in the same
+// order as lz_alpha, so the same bits), workgroup 0 records it, and the
+// update w = u - c3 q follows without a separate launch.
+template <class T>
+__global__ void __launch_bounds__(kBlock) lz_alpha_update(const HvTile *tiles, uint32_t n_tiles,
+                                                          const HvSector *secs, T *__restrict__ u,
+                                                          const T *__restrict__ q, LzDev d, int m,
+                                                          uint32_t s) {
+    __shared__ double red[kRedWaves];
+    __shared__ double c3s;
+    if (!d.active[s]) {
+        for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x)
+            if (threadIdx.x == 0) d.pn[tiles[ti].slot] = 0.0;
+        return;
+    }
+    const double sum = sector_sum(d.pd + secs[s].slot0, secs[s].nslots, red);
+    if (threadIdx.x == 0) {
+        const double a = d.c1[s] * sum;
+        c3s = a * d.c1[s];
+        if (blockIdx.x == 0) {
+            d.alpha[(size_t)s * m + d.steps[s]] = a;
+            d.c3[s] = c3s;
+        }
+    }
+    __syncthreads();
+    const T c = (T)c3s;
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const HvTile tl = tiles[ti];
+        const HvSector sc = secs[tl.sector];
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
+        const uint32_t rows = tl.nblk * sc.cdn;
+        double acc = 0;
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            T w = u[base + e] - c * q[base + e];
+            u[base + e] = w;
+            acc += (double)w * (double)w;
+        }
+        double bs = block_sum(acc, red);
+        if (threadIdx.x == 0) d.pn[tl.slot] = bs;
     }
 }
 
@@ -437,8 +489,12 @@ mbr_status enqueue_plain(mbr_lanczos *lz, int par, uint32_t s0, uint32_t nsec, u
     }
     MBR_TRY(hubbard_launch(lz->h, X, P, ep, s));
     const unsigned g = std::min<unsigned>(lz->grid, nt);
-    lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
-    lz_update<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, P, X, lz->dev);
+    if (nsec == 1) {
+        lz_alpha_update<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, P, X, lz->dev, lz->m, s0);
+    } else {
+        lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
+        lz_update<T><<<g, kBlock, 0, s>>>(tiles, nt, secs, P, X, lz->dev);
+    }
     lz_beta<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, default_tol(lz), 0, s0);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
