@@ -239,40 +239,93 @@ __global__ void lz_fill_zero(T *__restrict__ out, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (T)0;
 }
 
+// The reorthogonalising kernels move the rows of a tile (or merged group) as
+// 16-byte packs: the vectors share one stride that is a multiple of 64 rows,
+// so a row index decides the alignment of every vector alike.  A span is the
+// unaligned head, the run of whole packs and the tail; the at most
+// 2 * (kPack - 1) leftover rows go one to a thread.
+template <class T>
+struct alignas(16) Pack {
+    static constexpr int n = 16 / sizeof(T);
+    T e[n];
+};
+
+template <class T>
+__device__ __forceinline__ Pack<T> ld_pack(const T *p) {
+    return *reinterpret_cast<const Pack<T> *>(p);
+}
+
+template <class T>
+__device__ __forceinline__ void st_pack(T *p, const Pack<T> &v) {
+    *reinterpret_cast<Pack<T> *>(p) = v;
+}
+
+template <class T>
+struct Span {
+    uint64_t a0;    // first row of the first whole pack
+    uint32_t nv;    // whole packs
+    uint32_t head;  // rows before a0
+    uint32_t left;  // head + tail rows
+    uint64_t base;  // first row
+    __device__ Span(uint64_t b, uint32_t rows) : base(b) {
+        constexpr uint32_t n = Pack<T>::n;
+        head = (uint32_t)((n - b % n) % n);
+        if (head > rows) head = rows;
+        a0 = b + head;
+        nv = (rows - head) / n;
+        left = rows - nv * n;
+    }
+    // row of leftover t (t < left): head rows first, then the tail
+    __device__ uint64_t leftover(uint32_t t) const {
+        return t < head ? base + t : a0 + (uint64_t)nv * Pack<T>::n + (t - head);
+    }
+};
+
 // dst = c3 * w per sector.  With use_j the destination is basis vector j+1
 // (v_{j+1} = w / beta_j, only sectors still running); otherwise vector 0.
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_scale_into(const HvTile *tiles, uint32_t n_tiles,
                                                         const HvSector *secs, const T *__restrict__ w,
-                                                        T *__restrict__ V, uint64_t total, LzDev d,
+                                                        T *__restrict__ V, uint64_t ld, LzDev d,
                                                         int use_j) {
     const int64_t j = use_j ? (int64_t)(*d.j) + 1 : 0;
-    T *dst = V + (uint64_t)j * total;
+    T *dst = V + (uint64_t)j * ld;
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const HvTile tl = tiles[ti];
         if (use_j && !d.active[tl.sector]) continue;
         const HvSector sc = secs[tl.sector];
         const T c = (T)d.c3[tl.sector];
-        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
-        const uint32_t rows = tl.nblk * sc.cdn;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) dst[base + e] = w[base + e] * c;
+        const Span<T> sp(sc.off + (uint64_t)tl.rup0 * sc.cdn, tl.nblk * sc.cdn);
+        if (threadIdx.x < sp.left) {
+            const uint64_t r = sp.leftover(threadIdx.x);
+            dst[r] = w[r] * c;
+        }
+        for (uint32_t i = threadIdx.x; i < sp.nv; i += blockDim.x) {
+            const uint64_t r = sp.a0 + (uint64_t)i * Pack<T>::n;
+            Pack<T> v = ld_pack(w + r);
+#pragma unroll
+            for (int e = 0; e < Pack<T>::n; ++e) v.e[e] *= c;
+            st_pack(dst + r, v);
+        }
     }
 }
 
 // Reorthogonalising path: w = u - c3 v_j in place, then per-slot partials of
 // <v_k, w> for k = 0..j (classical Gram-Schmidt coefficients).  The basis
-// vectors are taken kKc at a time: one pass over the tile's rows reads kKc of
-// them (independent loads in flight) and one block reduction serves all kKc
-// sums.  Each sum is formed in the same order as a one-vector pass (per lane
-// in row order, then across the wave, then over the waves in order).
+// vectors are taken kKc at a time: one pass over the tile's rows loads a pack
+// of each of them together (a short last chunk repeats its last vector, whose
+// sums are then dropped) and one block reduction serves all kKc sums.  Each
+// sum is fixed-order: per lane (its leftover row, then its packs in order,
+// element by element), then across the wave, then over the waves in order.
 constexpr int kKc = 8;
 constexpr uint64_t kGroupRows = 4096;  // rows per merged group of the Gram-Schmidt kernels
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, uint32_t n_tiles,
                                                          const HvSector *secs, T *__restrict__ W,
-                                                         const T *__restrict__ V, uint64_t total,
+                                                         const T *__restrict__ V, uint64_t ld,
                                                          int m, LzDev d) {
+    constexpr int n = Pack<T>::n;
     __shared__ double red[kKc][kRedWaves];
     const int j = *d.j;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -281,22 +334,44 @@ __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, ui
         if (!d.active[tl.sector]) continue;
         double *pc = d.pc + (size_t)tl.slot * (m + 1);
         const HvSector sc = secs[tl.sector];
-        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
-        const uint32_t rows = tl.nblk * sc.cdn;
+        const Span<T> sp(sc.off + (uint64_t)tl.rup0 * sc.cdn, tl.nblk * sc.cdn);
         const T c = (T)d.c3[tl.sector];
-        const T *vj = V + (uint64_t)j * total;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) W[base + e] = W[base + e] - c * vj[base + e];
+        const T *vj = V + (uint64_t)j * ld;
+        const bool has_left = threadIdx.x < sp.left;
+        const uint64_t rl = has_left ? sp.leftover(threadIdx.x) : 0;
+        if (has_left) W[rl] = W[rl] - c * vj[rl];
+        for (uint32_t i = threadIdx.x; i < sp.nv; i += blockDim.x) {
+            const uint64_t r = sp.a0 + (uint64_t)i * n;
+            Pack<T> x = ld_pack(W + r);
+            const Pack<T> y = ld_pack(vj + r);
+#pragma unroll
+            for (int e = 0; e < n; ++e) x.e[e] = x.e[e] - c * y.e[e];
+            st_pack(W + r, x);
+        }
         __syncthreads();
         for (int k0 = 0; k0 <= j; k0 += kKc) {
             const int nk = (j + 1 - k0) < kKc ? (j + 1 - k0) : kKc;
+            const T *vk[kKc];
+#pragma unroll
+            for (int q = 0; q < kKc; ++q) vk[q] = V + (uint64_t)(k0 + (q < nk ? q : nk - 1)) * ld;
             double acc[kKc];
 #pragma unroll
             for (int q = 0; q < kKc; ++q) acc[q] = 0.0;
-            for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
-                const double w = (double)W[base + e];
+            if (has_left) {
+                const double x = (double)W[rl];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) acc[q] += (double)vk[q][rl] * x;
+            }
+            for (uint32_t i = threadIdx.x; i < sp.nv; i += blockDim.x) {
+                const uint64_t r = sp.a0 + (uint64_t)i * n;
+                const Pack<T> x = ld_pack(W + r);
+                Pack<T> v[kKc];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) v[q] = ld_pack(vk[q] + r);
 #pragma unroll
                 for (int q = 0; q < kKc; ++q)
-                    if (q < nk) acc[q] += (double)V[(uint64_t)(k0 + q) * total + base + e] * w;
+#pragma unroll
+                    for (int e = 0; e < n; ++e) acc[q] += (double)v[q].e[e] * (double)x.e[e];
             }
 #pragma unroll
             for (int q = 0; q < kKc; ++q) acc[q] = wave_sum(acc[q]);
@@ -314,29 +389,62 @@ __global__ void __launch_bounds__(kBlock) lz_update_dots(const HvTile *tiles, ui
     }
 }
 
-// Per-sector Gram-Schmidt coefficients: lane k sums the slot partials of
-// <v_k, w> in slot order.
-__global__ void lz_reduce_cgs(const HvSector *secs, LzDev d, int m, uint32_t s_first) {
+// Per-sector Gram-Schmidt coefficients.  Lanes take consecutive k (so the
+// slot rows are read coalesced) and the 16 waves split the slots: wave v adds
+// slots v, v + 16, ... (eight loads in flight), then thread k of wave 0 adds the
+// wave sums in wave order.  The order is fixed for a given slot count.
+constexpr unsigned kCgsBlock = 1024;
+
+__global__ void __launch_bounds__(kCgsBlock) lz_reduce_cgs(const HvSector *secs, LzDev d, int m,
+                                                           uint32_t s_first) {
+    constexpr int nw = kCgsBlock / 64;
+    __shared__ double part[nw][64];
     const uint32_t s = s_first + blockIdx.x;
     if (!d.active[s]) return;
     const int j = *d.j;
     const HvSector sc = secs[s];
-    for (int k = threadIdx.x; k <= j; k += blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const size_t ldp = (size_t)m + 1;
+    const double *p = d.pc + (size_t)sc.slot0 * ldp;
+    for (int k0 = 0; k0 <= j; k0 += 64) {
+        const int k = k0 + lane;
         double v = 0;
-        for (uint32_t i = 0; i < sc.nslots; ++i) v += d.pc[(size_t)(sc.slot0 + i) * (m + 1) + k];
-        d.cgs[(size_t)s * (m + 1) + k] = v;
+        if (k <= j) {
+            uint32_t i = wv;
+            for (; i + 7 * nw < sc.nslots; i += 8 * nw) {
+                double t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t[q] = p[(size_t)(i + q * nw) * ldp + k];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v += t[q];
+            }
+            for (; i < sc.nslots; i += nw) v += p[(size_t)i * ldp + k];
+        }
+        part[wv][lane] = v;
+        __syncthreads();
+        if (wv == 0 && k <= j) {
+            double sum = 0;
+            for (int w2 = 0; w2 < nw; ++w2) sum += part[w2][lane];
+            d.cgs[(size_t)s * ldp + k] = sum;
+        }
+        __syncthreads();
     }
 }
 
-// w -= sum_k c_k v_k (fp64 accumulation, k in order; the loads of kKc basis
-// vectors are issued together), then partial |w|^2.
+// w -= sum_k c_k v_k (fp64 accumulation, k in order), then partial |w|^2.  The
+// block stages c_0..c_j in LDS followed by kKc - 1 zeros, so every chunk of kKc
+// basis vectors is whole: a vector past j is read at index j and subtracted
+// with coefficient 0, which leaves w unchanged.  Dynamic LDS: (m + kKc) doubles.
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_subtract(const HvTile *tiles, uint32_t n_tiles,
                                                       const HvSector *secs, T *__restrict__ W,
-                                                      const T *__restrict__ V, uint64_t total, int m,
+                                                      const T *__restrict__ V, uint64_t ld, int m,
                                                       LzDev d) {
+    constexpr int n = Pack<T>::n;
     __shared__ double red[kRedWaves];
+    extern __shared__ double cs[];
     const int j = *d.j;
+    const int kend = j + 1 + kKc - 1;  // staged coefficients (c_0..c_j, then zeros)
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const HvTile tl = tiles[ti];
         if (!d.active[tl.sector]) {
@@ -344,26 +452,47 @@ __global__ void __launch_bounds__(kBlock) lz_subtract(const HvTile *tiles, uint3
             continue;
         }
         const HvSector sc = secs[tl.sector];
-        const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
-        const uint32_t rows = tl.nblk * sc.cdn;
+        const Span<T> sp(sc.off + (uint64_t)tl.rup0 * sc.cdn, tl.nblk * sc.cdn);
         const double *c = d.cgs + (size_t)tl.sector * (m + 1);
+        __syncthreads();  // the previous tile's readers of cs are done
+        for (int k = threadIdx.x; k < kend; k += blockDim.x) cs[k] = k <= j ? c[k] : 0.0;
+        __syncthreads();
         double acc = 0;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
-            double w = (double)W[base + e];
-            int k = 0;
-            for (; k + kKc <= j + 1; k += kKc) {
-                T v[kKc];
-#pragma unroll
-                for (int q = 0; q < kKc; ++q) v[q] = V[(uint64_t)(k + q) * total + base + e];
-#pragma unroll
-                for (int q = 0; q < kKc; ++q) w -= c[k + q] * (double)v[q];
-            }
-            for (; k <= j; ++k) w -= c[k] * (double)V[(uint64_t)k * total + base + e];
-            T wt = (T)w;
-            W[base + e] = wt;
+        if (threadIdx.x < sp.left) {
+            const uint64_t r = sp.leftover(threadIdx.x);
+            double w = (double)W[r];
+            for (int k = 0; k <= j; ++k) w -= cs[k] * (double)V[(uint64_t)k * ld + r];
+            const T wt = (T)w;
+            W[r] = wt;
             acc += (double)wt * (double)wt;
         }
-        double s = block_sum(acc, red);
+        for (uint32_t i = threadIdx.x; i < sp.nv; i += blockDim.x) {
+            const uint64_t r = sp.a0 + (uint64_t)i * n;
+            const Pack<T> x = ld_pack(W + r);
+            double w[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) w[e] = (double)x.e[e];
+            for (int k0 = 0; k0 <= j; k0 += kKc) {
+                Pack<T> v[kKc];
+#pragma unroll
+                for (int q = 0; q < kKc; ++q) {
+                    const int k = k0 + q <= j ? k0 + q : j;
+                    v[q] = ld_pack(V + (uint64_t)k * ld + r);
+                }
+#pragma unroll
+                for (int q = 0; q < kKc; ++q)
+#pragma unroll
+                    for (int e = 0; e < n; ++e) w[e] -= cs[k0 + q] * (double)v[q].e[e];
+            }
+            Pack<T> o;
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                o.e[e] = (T)w[e];
+                acc += (double)o.e[e] * (double)o.e[e];
+            }
+            st_pack(W + r, o);
+        }
+        const double s = block_sum(acc, red);
         if (threadIdx.x == 0) d.pn[tl.slot] = s;
     }
 }
@@ -435,6 +564,7 @@ struct mbr_lanczos {
     int ns = 0, m = 0, prec = MBR_F64;
     size_t tsz = 8;
     uint64_t total = 0;
+    uint64_t ld = 0;  // stride of the stored basis vectors (total rounded up to 64 rows)
     uint32_t n_slots = 0;
     std::vector<HvSector> secs;
     DevBuf d_tiles_slot, d_secs;
@@ -514,7 +644,7 @@ mbr_status enqueue_reorth(mbr_lanczos *lz, uint32_t s0, uint32_t nsec, uint32_t 
     ep.partial = lz->dev.pd;
     ep.active = lz->dev.active;
     ep.basis_j = lz->dev.j;
-    ep.basis_stride = lz->total;
+    ep.basis_stride = lz->ld;
     if (!all) {
         ep.tiles = tiles;
         ep.n_tiles = nt;
@@ -530,11 +660,12 @@ mbr_status enqueue_reorth(mbr_lanczos *lz, uint32_t s0, uint32_t nsec, uint32_t 
     const unsigned g = all ? std::max<unsigned>(1, std::min<unsigned>(gn, 1u << 20))
                            : std::min<unsigned>(lz->grid, gn);
     lz_alpha<<<nsec, kBlock, 0, s>>>(secs, lz->dev, lz->m, s0);
-    lz_update_dots<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->m, lz->dev);
-    lz_reduce_cgs<<<nsec, kBlock, 0, s>>>(rsecs, lz->dev, lz->m, s0);
-    lz_subtract<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->m, lz->dev);
+    lz_update_dots<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->ld, lz->m, lz->dev);
+    lz_reduce_cgs<<<nsec, kCgsBlock, 0, s>>>(rsecs, lz->dev, lz->m, s0);
+    lz_subtract<T><<<g, kBlock, (size_t)(lz->m + kKc) * sizeof(double), s>>>(groups, gn, rsecs, W, V, lz->ld,
+                                                                           lz->m, lz->dev);
     lz_beta<<<nsec, kBlock, 0, s>>>(rsecs, lz->dev, lz->m, default_tol(lz), 1, s0);
-    lz_scale_into<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->total, lz->dev, 1);
+    lz_scale_into<T><<<g, kBlock, 0, s>>>(groups, gn, rsecs, W, V, lz->ld, lz->dev, 1);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
@@ -594,7 +725,7 @@ mbr_status lz_start_t(mbr_lanczos *lz, const double *v0, hipStream_t s) {
     lz_start_scalars<<<lz->ns, kBlock, 0, s>>>(secs, lz->dev, reorth ? 1 : 0);
     if (reorth)
         lz_scale_into<T><<<lz->grid, kBlock, 0, s>>>(tiles, lz->n_slots, secs, X, lz->basis.as<T>(),
-                                                      lz->total, lz->dev, 0);
+                                                      lz->ld, lz->dev, 0);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
@@ -617,6 +748,7 @@ mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o, m
     lz->prec = hubbard_precision(h);
     lz->tsz = lz->prec == MBR_F64 ? 8 : 4;
     lz->total = hubbard_total(h);
+    lz->ld = (lz->total + 63) / 64 * 64;
     lz->n_slots = hubbard_n_slots(h);
     lz->secs = hubbard_sectors(h);
     lz->generation = hubbard_generation(h);
@@ -658,9 +790,9 @@ mbr_status mbr_lanczos_create(const mbr_hubbard *h, const mbr_lanczos_opts *o, m
     }
     const size_t ns = lz->ns, m = lz->m, nsl = lz->n_slots;
     if (o->reorth) {
-        const double bytes = (double)lz->total * lz->tsz * (m + 2);
+        const double bytes = (double)lz->ld * lz->tsz * (m + 2);
         if (bytes > 250e9) MBR_FAIL(MBR_ENOMEM, "basis of %.1f GB", bytes / 1e9);
-        MBR_TRY(lz->basis.alloc(lz->total * lz->tsz * (m + 1)));
+        MBR_TRY(lz->basis.alloc(lz->ld * lz->tsz * (m + 1)));
         MBR_TRY(lz->work.alloc(lz->total * lz->tsz));
         MBR_TRY(lz->pc.alloc(nsl * (m + 1) * 8));
         MBR_TRY(lz->cgs.alloc(ns * (m + 1) * 8));
