@@ -457,6 +457,7 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
 // the tile kernel, so both give bitwise identical products.
 // ------------------------------------------------------------------------
 constexpr int kRowsBlock = 1024;
+constexpr int kRowsWaves = kRowsBlock / 64;
 constexpr int kRowsNB = 16;           // bonds
 constexpr int kRowsMaxG = 64;         // alpha_up blocks per tile when C_dn is small
 constexpr int kRowsMaxR = 4;          // alpha_dn per lane
@@ -942,9 +943,13 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 }
             }
         }
+        // tile partial of <q_j, u>: each wave leaves its sum in this tile's half
+        // of red; after the barrier below wave 0 adds the 16 of them (a fixed
+        // tree) while the other waves go on, so the tile costs no extra barrier
         if (a.ep.partial) {
-            const double sum = block_sum(dot, red);
-            if (threadIdx.x == 0) a.ep.partial[c.slot] = active ? sum : 0.0;
+            double v = dot;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if ((tid & 63) == 0) red[buf * kRowsWaves + (tid >> 6)] = v;
         }
         // next tile: up-hop targets, negated copy of the staged rows, zeros
         if (has_next) {
@@ -952,6 +957,12 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
             rows_pre_store<T>(nb2, LL.cs, n.nblk, n.cdn, pre);
         }
         __syncthreads();
+        if (a.ep.partial && tid < 64) {
+            // red[buf] is rewritten two tiles on, after the next barrier
+            double v = tid < kRowsWaves ? red[buf * kRowsWaves + tid] : 0.0;
+            for (int o = kRowsWaves / 2; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (tid == 0) a.ep.partial[c.slot] = active ? v : 0.0;
+        }
         qc[0] = qn[0];
         qc[1] = qn[1];
         qn[0] = qnn[0];
