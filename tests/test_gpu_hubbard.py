@@ -184,6 +184,46 @@ def test_lanczos_all_sectors_reorth(prec, tol, batched):
         assert nst[si] <= st.size
 
 
+@pytest.mark.parametrize("batched", [True, False])
+def test_lanczos_reorth_early_coefficients_match_plain_recurrence(batched):
+    """The Gram-Schmidt passes change nothing while the basis is still
+    orthogonal to rounding: the first coefficients of the reorthogonalising
+    path equal those of the oracle's plain three-term recurrence.  Sector
+    sizes C(8, n_up) C(8, n_dn) give every alignment of the sector offsets."""
+    L, U = 8, 3.0
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), sectors, U=[U] * L)
+    e0, nst, a, b = _run_lanczos(h, 12, seed=21, reorth=True, batched=batched)
+    v0 = synth.start_vector(21, h.dim)
+    tl = OH.terms(L, OH.chain_bonds(L), U)
+    for si, (nu, nd) in enumerate(sectors):
+        st = OH.sector(L, nu, nd)
+        A = OH.sparse(st, tl)
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        n = min(6, int(nst[si]) - 1)
+        if n <= 0:
+            continue
+        oa, ob = OL.lanczos(lambda v: A @ v, v0[o0:o1], n)
+        scale = max(1.0, float(np.abs(oa[:n]).max()))
+        assert np.allclose(a[si, :n], oa[:n], rtol=0, atol=1e-10 * scale), (nu, nd)
+        assert np.allclose(b[si, :n], ob[:n], rtol=0, atol=1e-10 * scale), (nu, nd)
+
+
+def test_lanczos_reorth_300_steps_against_sparse_eigensolver():
+    """Three hundred steps with full Gram-Schmidt on sectors of 4,900 and 3,920
+    states: many whole chunks of eight basis vectors and short last chunks."""
+    L, U = 8, 3.0
+    sectors = [(4, 4), (3, 4)]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), sectors, U=[U] * L)
+    e0, nst, _, _ = _run_lanczos(h, 300, seed=8, reorth=True)
+    tl = OH.terms(L, OH.chain_bonds(L), U)
+    for si, (nu, nd) in enumerate(sectors):
+        A = OH.sparse(OH.sector(L, nu, nd), tl)
+        want = OL.lowest_eigenvalue(A)
+        assert nst[si] > 256
+        assert abs(e0[si] - want) <= 1e-9 * abs(want), (nu, nd, e0[si], want)
+
+
 def test_lanczos_graph_batched_and_repeat_are_bitwise_equal():
     L = 8
     sectors = [(4, 4), (3, 5), (1, 1), (8, 0)]
