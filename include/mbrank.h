@@ -160,6 +160,18 @@ mbr_status mbr_staggered_table_copy(const mbr_ranker *r, uint64_t *host_out, uin
 mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t k,
                                  mbr_ranker **out, void *stream);
 
+/* Unrank in the spin sector of a spin ranker without its state list (the
+ * inverse of Eq. rankupdown, each half by Eq. unrank):
+ * d_out[j] = (half_up << L) | half_dn with half_up the (i / C(L, n_dn))-th and
+ * half_dn the (i mod C(L, n_dn))-th ascending pattern of n_up (n_dn) set bits
+ * among L, i = d_idx[j]; all ones when i >= C(L, n_up) C(L, n_dn).  d_out has
+ * the ranker's width (32 bits for L <= 16, else 64).  The halves come from
+ * lists staged in LDS when both are short (L <= 16, at most 32768 patterns
+ * together), else from the greedy inversion of Eq. cns over a binomial table
+ * in LDS.  EINVAL for a ranker of another kind. */
+mbr_status mbr_unrank_spin_batch(const mbr_ranker *r, const uint32_t *d_idx, uint64_t n, void *d_out,
+                                 void *stream);
+
 /* Packed radix-2^k trie over a sector (Sec. IV, Fig. trie, Fig. trielookup):
  * chunks dispatched from the least significant end, one array per level, each
  * node spanning its first to last occurring child, unused slots zero and the

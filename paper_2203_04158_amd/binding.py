@@ -94,6 +94,7 @@ _SIGS = {
     "mbr_sector_states": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mbr_sector_destroy": (C.c_int32, [C.c_void_p]),
     "mbr_unrank_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "mbr_unrank_spin_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_build_staggered_tables": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                                C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_staggered_table_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64,
@@ -297,6 +298,17 @@ def build_spin_ranker(L: int, n_up: int, n_dn: int, k: int, stream=None) -> Rank
     _check("mbr_build_spin_ranker",
            lib().mbr_build_spin_ranker(L, n_up, n_dn, k, C.byref(h), _stream(stream)))
     return Ranker(h)
+
+
+def unrank_spin_batch(ranker: Ranker, idx, out=None, stream=None):
+    """Patterns of the spin ranker's sector at int32 device indices `idx`."""
+    torch = _torch()
+    if out is None:
+        dt = torch.int32 if ranker.info().width_bits == 32 else torch.int64
+        out = torch.empty(idx.numel(), dtype=dt, device="cuda")
+    _check("mbr_unrank_spin_batch", lib().mbr_unrank_spin_batch(ranker.handle, _dptr(idx), idx.numel(),
+                                                                _dptr(out), _stream(stream)))
+    return out
 
 
 def build_trie(sector: Sector, k: int, stream=None) -> Ranker:

@@ -155,6 +155,8 @@ struct mbr_ranker {
     bool rank64 = false;       // staggered: ranks only fit the 64-bit entry point
     int device = 0;
     StagTable stag;            // staggered, spin halves
+    mbr::DevBuf unrank_tab;    // spin: half lists (uint16) or binomial table for unranking
+    bool unrank_lists = false; // spin: unrank_tab holds the half lists
     TrieLevels *trie = nullptr;
     LearnedModel *learned = nullptr;
     const mbr_sector *sector = nullptr;
@@ -175,6 +177,8 @@ mbr_status rank_staggered_launch64(const mbr_ranker *r, const void *q, uint64_t 
                                    hipStream_t s);
 mbr_status rank_bisect_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                               hipStream_t s);
+// Unranking tables of a spin ranker (unrank.hip).
+mbr_status spin_unrank_build(mbr_ranker *r, hipStream_t s);
 mbr_status rank_cns_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                            hipStream_t s);
 void trie_free(TrieLevels *t);

@@ -463,6 +463,7 @@ mbr_status mbr_build_spin_ranker(int32_t L, int32_t n_up, int32_t n_dn, int32_t 
     int eb = entry_bytes_for(L, nmax);
     if ((L + k - 1) / k > 16) MBR_FAIL_DEL(r, MBR_EUNSUPPORTED, "more than 16 chunks");
     mbr_status st = stag_build(r->stag, L, k, nmax, eb, as_stream(stream));
+    if (st == MBR_OK) st = spin_unrank_build(r, as_stream(stream));
     if (st != MBR_OK) {
         delete r;
         return st;

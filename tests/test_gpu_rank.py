@@ -174,3 +174,66 @@ def test_rank_ragged_and_unaligned(kind, qoff, ooff, n):
     out = torch.full((n + ooff,), 7, dtype=torch.int32, device="cuda")[ooff:]
     mbr.rank_batch(r, qd, out=out)
     assert np.array_equal(host_rank(out), want[qoff:])
+
+
+@pytest.mark.parametrize("L,nu,nd", [(6, 3, 2), (6, 0, 6), (6, 6, 0), (1, 1, 0), (12, 5, 6),
+                                     (14, 7, 7), (17, 3, 4), (19, 1, 9), (20, 2, 3)])
+def test_unrank_spin_matches_sector_list(L, nu, nd):
+    """Every index of the spin sector (L <= 16: half lists in LDS; L > 16:
+    greedy combinadics) against the oracle's ascending sector list, plus
+    indices past the end."""
+    st = OC.sector_enumerate(2 * L, OC.spin_constraints(L, nu, nd))
+    r = mbr.build_spin_ranker(L, nu, nd, min(L, 8))
+    wide = 2 * L > 32
+    idx = np.concatenate([np.arange(st.size, dtype=np.uint64),
+                          np.array([st.size, st.size + 1, 0xFFFFFFFE], dtype=np.uint64)])
+    out = mbr.unrank_spin_batch(r, dev_u32(idx))
+    got = host_u64(out) if wide else host_u32(out)
+    ones = np.uint64(0xFFFFFFFFFFFFFFFF if wide else 0xFFFFFFFF)
+    assert np.array_equal(got[:st.size], st)
+    assert (got[st.size:] == ones).all()
+
+
+def test_unrank_spin_l16_full_size_round_trip():
+    """(8,8) on 16 sites (165,636,900 states, no list stored): 2^22 uniform
+    indices; each pattern has the sector's popcounts, ranks back to its index
+    on the GPU, and sampled ones match the oracle's combinadics of each half
+    composed by Eq. rankupdown."""
+    L, nu, nd = 16, 8, 8
+    n_dn = OC.binom(L, nd)
+    total = OC.binom(L, nu) * n_dn
+    r = mbr.build_spin_ranker(L, nu, nd, 8)
+    idx = synth.uniform_indices(7, 1 << 22, total).astype(np.uint64)
+    idx[:3] = [0, total - 1, total // 2]
+    pat = mbr.unrank_spin_batch(r, dev_u32(idx))
+    back = host_rank(mbr.rank_batch(r, pat))
+    assert np.array_equal(back, idx.astype(np.int64))
+    p = host_u32(pat)
+    lo, hi = p & np.uint64(0xFFFF), p >> np.uint64(16)
+    pc = lambda v: np.array([bin(int(t)).count("1") for t in v[:4096]])
+    assert (pc(lo) == nd).all() and (pc(hi) == nu).all()
+    for t in range(0, 4096, 37):
+        i = int(idx[t])
+        assert OC.cns_rank(int(hi[t])) * n_dn + OC.cns_rank(int(lo[t])) == i
+
+
+def test_unrank_spin_l32_sampled():
+    """64-bit patterns on 32 sites, (3,2): sampled indices against the oracle's
+    Eq. unrank of each half composed by Eq. rankupdown."""
+    L, nu, nd = 32, 3, 2
+    n_dn = OC.binom(L, nd)
+    total = OC.binom(L, nu) * n_dn
+    r = mbr.build_spin_ranker(L, nu, nd, 8)
+    idx = synth.uniform_indices(11, 3000, total).astype(np.uint64)
+    idx[:2] = [0, total - 1]
+    got = host_u64(mbr.unrank_spin_batch(r, dev_u32(idx)))
+    for t, i in enumerate(idx):
+        i = int(i)
+        want = (OC.cns_unrank(i // n_dn, nu, L) << L) | OC.cns_unrank(i % n_dn, nd, L)
+        assert int(got[t]) == want, (i, hex(int(got[t])), hex(want))
+
+
+def test_unrank_spin_rejects_other_rankers():
+    r = mbr.build_staggered_tables(12, 6, 6)
+    with pytest.raises(mbr.MbrError):
+        mbr.unrank_spin_batch(r, dev_u32(np.arange(4, dtype=np.uint64)))
