@@ -50,7 +50,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
-ROWS = ("staggered", "staggered64", "trie", "learned", "batched", "operator")
+ROWS = ("staggered", "unrank", "staggered64", "trie", "learned", "batched", "operator")
 EXTRA_ROWS = ("sweep",)   # run only when asked for by name
 
 
@@ -176,6 +176,43 @@ def row_staggered(torch, mbr, reps):
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
             "roofline": roof, "stress_2e28": stress}
+
+
+def row_unrank(torch, mbr, reps):
+    """Unrank (Sec. II, Eq. unrank) of 2^24 uniform indices: through the stored
+    list (a random gather per query) in the M=24 N=12 sector and in the L=14
+    (7,7) spin sector, and without a list in the spin sectors L=14 (7,7) and
+    L=16 (8,8) (both halves from LDS, Eq. rankupdown inverted).  Checked by
+    ranking the patterns back (staggered or spin-resolved ranks)."""
+    import synth
+    nq = 1 << 24
+    h14 = (1 << 14) - 1
+    res = {"workload": "2^24 uniform indices per case; list gathers in M=24 N=12 (2,704,156 states, "
+                       "10.8 MB list) and L=14 (7,7) (11,778,624 states, 47 MB); list-free spin unrank "
+                       "in L=14 (7,7) and L=16 (8,8) (165,636,900 states)"}
+    for name, M, cons, ranker in (
+            ("list_m24_n12", 24, [(full_mask(24), 12, 12)], lambda: mbr.build_staggered_tables(24, 12, 8)),
+            ("list_chain_7x7", 28, [(full_mask(28), 14, 14), (h14, 7, 7), (h14 << 14, 7, 7)],
+             lambda: mbr.build_spin_ranker(14, 7, 7, 7))):
+        s = mbr.sector_build(M, cons)
+        idx = torch.from_numpy(synth.uniform_indices(40 + M, nq, s.size).astype(np.int32)).cuda()
+        out = torch.empty(nq, dtype=torch.int32, device="cuda")
+        ms = time_launches(torch, lambda: mbr.unrank_batch(s, idx, out=out), reps)
+        exact = bool(torch.equal(mbr.rank_batch(ranker(), out), idx))
+        res[name] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Gunranks/s", "kernel_ms": ms, "exact": exact,
+                     "roofline": hbm_roofline(8.0 * nq, ms, "unrank_kernel (4 B index in, 4 B pattern out; "
+                                              "the list gather comes on top)")}
+        del s
+    for name, L_, nu, nd in (("spin_chain_7x7", 14, 7, 7), ("spin_l16_8x8", 16, 8, 8)):
+        r = mbr.build_spin_ranker(L_, nu, nd, 8)
+        total = math.comb(L_, nu) * math.comb(L_, nd)
+        idx = torch.from_numpy(synth.uniform_indices(50 + L_, nq, total).astype(np.int32)).cuda()
+        out = torch.empty(nq, dtype=torch.int32, device="cuda")
+        ms = time_launches(torch, lambda: mbr.unrank_spin_batch(r, idx, out=out), reps)
+        exact = bool(torch.equal(mbr.rank_batch(r, out), idx))
+        res[name] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Gunranks/s", "kernel_ms": ms, "exact": exact,
+                     "roofline": hbm_roofline(8.0 * nq, ms, "unrank_spin_kernel (4 B index in, 4 B pattern out)")}
+    return res
 
 
 def row_staggered64(torch, mbr, reps):
@@ -574,6 +611,8 @@ def main():
         t0 = time.perf_counter()
         if r == "staggered":
             extra[r] = row_staggered(torch, mbr, 50)
+        elif r == "unrank":
+            extra[r] = row_unrank(torch, mbr, 20)
         elif r == "staggered64":
             extra[r] = row_staggered64(torch, mbr, 20)
         elif r == "trie":
