@@ -19,7 +19,9 @@
 
 namespace {
 
-constexpr unsigned kBlock = 256;
+// Large workgroups, two per CU, each staging its table once: the uint16 lists
+// of L = 16 take 51.5 KB, and two such workgroups still fill a CU with 32 waves.
+constexpr unsigned kBlock = 1024;
 constexpr int kQ = 4;                        // queries in flight per lane
 constexpr uint32_t kMaxListEntries = 32768;  // uint16 half lists: 64 KB of LDS
 
@@ -45,43 +47,62 @@ __device__ __forceinline__ uint32_t half_unrank(uint32_t r, int N, const uint32_
     return x;
 }
 
-template <class P, bool LISTS>
+// V queries per lane and vector access: a V-wide load of indices and one
+// 16-byte store of patterns (V = 16 / sizeof(P)); V = 1 when the buffers are
+// not so aligned.  The first indices are loaded before the table is staged.
+template <class P, bool LISTS, int V>
 __global__ void __launch_bounds__(kBlock) unrank_spin_kernel(const uint32_t *__restrict__ idx, uint64_t n,
                                                              P *__restrict__ out,
                                                              const void *__restrict__ gtab, uint32_t tab_bytes,
                                                              SpinUnrankArgs a) {
+    typedef uint32_t ivec __attribute__((ext_vector_type(V)));
+    typedef P pvec __attribute__((ext_vector_type(V)));
     extern __shared__ __align__(16) unsigned char lds[];
-    stage_to_lds(lds, gtab, tab_bytes);
-    __syncthreads();
     const uint16_t *lists = reinterpret_cast<const uint16_t *>(lds);
     const uint32_t *bt = reinterpret_cast<const uint32_t *>(lds);
+    auto one = [&](uint32_t i) -> P {
+        if (i >= a.total) return ~(P)0;
+        const uint32_t ru = i / a.cdn, rd = i - ru * a.cdn;
+        uint32_t hu, hd;
+        if constexpr (LISTS) {
+            hu = lists[ru];
+            hd = lists[a.cup + rd];
+        } else {
+            hu = half_unrank(ru, a.n_up, bt, a.L);
+            hd = half_unrank(rd, a.n_dn, bt, a.L);
+        }
+        return ((P)hu << a.L) | (P)hd;
+    };
+    const uint64_t nv = n / V;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; base < n; base += stride * kQ) {
-        uint32_t i[kQ];
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    ivec iv[kQ];
+    auto load = [&](uint64_t base) {
 #pragma unroll
         for (int u = 0; u < kQ; ++u) {
             const uint64_t j = base + u * stride;
-            i[u] = j < n ? idx[j] : 0u;
+            if (j < nv) iv[u] = reinterpret_cast<const ivec *>(idx)[j];
         }
+    };
+    load(t0);
+    stage_to_lds(lds, gtab, tab_bytes);
+    __syncthreads();
+    for (uint64_t base = t0; base < nv; base += stride * kQ) {
+        if (base != t0) load(base);
 #pragma unroll
         for (int u = 0; u < kQ; ++u) {
             const uint64_t j = base + u * stride;
-            if (j >= n) continue;
-            P x = ~(P)0;
-            if (i[u] < a.total) {
-                const uint32_t ru = i[u] / a.cdn, rd = i[u] - ru * a.cdn;
-                uint32_t hu, hd;
-                if constexpr (LISTS) {
-                    hu = lists[ru];
-                    hd = lists[a.cup + rd];
-                } else {
-                    hu = half_unrank(ru, a.n_up, bt, a.L);
-                    hd = half_unrank(rd, a.n_dn, bt, a.L);
-                }
-                x = ((P)hu << a.L) | (P)hd;
+            if (j < nv) {
+                pvec o;
+#pragma unroll
+                for (int e = 0; e < V; ++e) o[e] = one(iv[u][e]);
+                reinterpret_cast<pvec *>(out)[j] = o;
             }
-            out[j] = x;
         }
+    }
+    if (t0 < n - nv * V) {
+        const uint64_t j = nv * V + t0;
+        out[j] = one(idx[j]);
     }
 }
 
@@ -97,8 +118,8 @@ void append_half(std::vector<uint16_t> &v, int L, int N) {
     }
 }
 
-template <class P, bool LISTS>
-mbr_status launch(const mbr_ranker *r, const uint32_t *d_idx, uint64_t n, void *d_out, hipStream_t s) {
+template <class P, bool LISTS, int V>
+mbr_status launch_v(const mbr_ranker *r, const uint32_t *d_idx, uint64_t n, void *d_out, hipStream_t s) {
     SpinUnrankArgs a{};
     a.total = r->n_states;
     a.cup = (uint32_t)mbr::binom(r->L, r->n_up);
@@ -106,12 +127,20 @@ mbr_status launch(const mbr_ranker *r, const uint32_t *d_idx, uint64_t n, void *
     a.L = r->L;
     a.n_up = r->n_up;
     a.n_dn = r->n_dn;
-    const unsigned grid = mbr::grid_for(n, kBlock * kQ, mbr::device_cu_count() * 8);
+    const unsigned grid = mbr::grid_for((n + V - 1) / V, kBlock * kQ, mbr::device_cu_count() * 2);
     const uint32_t bytes = (uint32_t)r->unrank_tab.bytes;
-    unrank_spin_kernel<P, LISTS><<<grid, kBlock, bytes, s>>>(d_idx, n, static_cast<P *>(d_out),
-                                                              r->unrank_tab.p, bytes, a);
+    unrank_spin_kernel<P, LISTS, V><<<grid, kBlock, bytes, s>>>(d_idx, n, static_cast<P *>(d_out),
+                                                                 r->unrank_tab.p, bytes, a);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
+}
+
+template <class P, bool LISTS>
+mbr_status launch(const mbr_ranker *r, const uint32_t *d_idx, uint64_t n, void *d_out, hipStream_t s) {
+    constexpr int V = 16 / sizeof(P);
+    const bool aligned = reinterpret_cast<uintptr_t>(d_idx) % (4 * V) == 0 &&
+                         reinterpret_cast<uintptr_t>(d_out) % 16 == 0;
+    return aligned ? launch_v<P, LISTS, V>(r, d_idx, n, d_out, s) : launch_v<P, LISTS, 1>(r, d_idx, n, d_out, s);
 }
 
 }  // namespace

@@ -237,3 +237,24 @@ def test_unrank_spin_rejects_other_rankers():
     r = mbr.build_staggered_tables(12, 6, 6)
     with pytest.raises(mbr.MbrError):
         mbr.unrank_spin_batch(r, dev_u32(np.arange(4, dtype=np.uint64)))
+
+
+@pytest.mark.parametrize("L,nu,nd", [(12, 5, 6), (18, 2, 3)])
+@pytest.mark.parametrize("qoff,ooff,n", [(0, 0, 1), (0, 0, 4099), (1, 0, 4097), (0, 3, 10001),
+                                         (2, 1, 70001), (0, 0, 1 << 20)])
+def test_unrank_spin_ragged_and_unaligned(L, nu, nd, qoff, ooff, n):
+    """Vector (16-byte) and scalar access paths: sizes with a ragged tail, and
+    index / output views that start off the vector alignment."""
+    import torch
+    st = OC.sector_enumerate(2 * L, OC.spin_constraints(L, nu, nd))
+    r = mbr.build_spin_ranker(L, nu, nd, 6)
+    idx = synth.uniform_indices(n + qoff, n, st.size + 5).astype(np.uint64)  # a few past the end
+    qbuf = dev_u32(np.concatenate([np.zeros(qoff, np.uint64), idx]))
+    wide = 2 * L > 32
+    obuf = torch.empty(n + ooff, dtype=torch.int64 if wide else torch.int32, device="cuda")
+    mbr.unrank_spin_batch(r, qbuf[qoff:], out=obuf[ooff:])
+    got = host_u64(obuf[ooff:]) if wide else host_u32(obuf[ooff:])
+    ones = np.uint64(0xFFFFFFFFFFFFFFFF if wide else 0xFFFFFFFF)
+    inside = idx < st.size
+    assert np.array_equal(got[inside], st[idx[inside]])
+    assert (got[~inside] == ones).all()
