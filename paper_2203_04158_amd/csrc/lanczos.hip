@@ -243,7 +243,7 @@ __global__ void lz_fill_zero(T *__restrict__ out, uint64_t n) {
 // 16-byte packs: the vectors share one stride that is a multiple of 64 rows,
 // so a row index decides the alignment of every vector alike.  A span is the
 // unaligned head, the run of whole packs and the tail; its leftover rows (at
-// most twice the pack's element count less one) go one to a thread.
+// most 2 (n - 1) for n elements per pack) go one to a thread.
 template <class T>
 struct alignas(16) Pack {
     static constexpr int n = 16 / sizeof(T);
