@@ -86,9 +86,20 @@ def cpu_baseline(budget_s: float):
     OH.apply(st, tl, x, row_range=(0, rows))
     dt = time.perf_counter() - t0
     rate = rows / dt / st.size
+    # context for the ranking rows: the oracle's bisection and combinadics
+    # ranks of the staggered row's workload (M=24, N=12, 2^22 member queries)
+    from oracle import combinatorics as OC
+    sec = OC.sector_enumerate(24, OC.constraints(24, 12))
+    q = sec[synth.uniform_indices(1, 1 << 22, sec.size)]
+    ranks = {}
+    for name, fn in (("bisect", lambda: OC.bisect_rank(sec, q)), ("cns", lambda: OC.cns_rank_batch(q))):
+        t0 = time.perf_counter()
+        fn()
+        ranks[name] = {"value": q.size / (time.perf_counter() - t0) / 1e9, "unit": "Granks/s", "cores": 1}
     return {"value": rate, "unit": "H·v/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle H·x over rows 0..{rows - 1} of {st.size} ({dt:.1f} s, 1 thread), "
-                      f"scaled to whole products"}
+                      f"scaled to whole products",
+            "rank_m24_n12_2e22": ranks}
 
 
 # --------------------------------------------------------------------------- helpers
