@@ -191,6 +191,19 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _dvec(t, itemsize: int, n: int, what: str):
+    """Device pointer of `t` after checking that it is a contiguous device
+    tensor of `itemsize`-byte elements holding at least `n` of them (the C ABI
+    takes raw pointers and cannot check sizes)."""
+    if t is None or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous device tensor")
+    if t.element_size() != itemsize:
+        raise ValueError(f"{what}: expected {itemsize}-byte elements, got {t.element_size()}")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} elements, need {n}")
+    return C.c_void_p(t.data_ptr())
+
+
 def _torch():
     import torch
     return torch
@@ -248,8 +261,10 @@ def unrank_batch(sector: Sector, idx, out=None, stream=None):
     if out is None:
         dt = torch.int32 if sector.width_bits == 32 else torch.int64
         out = torch.empty(idx.numel(), dtype=dt, device="cuda")
-    _check("mbr_unrank_batch", lib().mbr_unrank_batch(sector.handle, _dptr(idx), idx.numel(),
-                                                      _dptr(out), _stream(stream)))
+    n = idx.numel()
+    _check("mbr_unrank_batch", lib().mbr_unrank_batch(sector.handle, _dvec(idx, 4, n, "idx"), n,
+                                                      _dvec(out, sector.width_bits // 8, n, "out"),
+                                                      _stream(stream)))
     return out
 
 
@@ -303,11 +318,13 @@ def build_spin_ranker(L: int, n_up: int, n_dn: int, k: int, stream=None) -> Rank
 def unrank_spin_batch(ranker: Ranker, idx, out=None, stream=None):
     """Patterns of the spin ranker's sector at int32 device indices `idx`."""
     torch = _torch()
+    width = ranker.info().width_bits
     if out is None:
-        dt = torch.int32 if ranker.info().width_bits == 32 else torch.int64
-        out = torch.empty(idx.numel(), dtype=dt, device="cuda")
-    _check("mbr_unrank_spin_batch", lib().mbr_unrank_spin_batch(ranker.handle, _dptr(idx), idx.numel(),
-                                                                _dptr(out), _stream(stream)))
+        out = torch.empty(idx.numel(), dtype=torch.int32 if width == 32 else torch.int64, device="cuda")
+    n = idx.numel()
+    _check("mbr_unrank_spin_batch", lib().mbr_unrank_spin_batch(ranker.handle, _dvec(idx, 4, n, "idx"), n,
+                                                                _dvec(out, width // 8, n, "out"),
+                                                                _stream(stream)))
     return out
 
 
@@ -375,8 +392,9 @@ def mlp_forward(params, q, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty(q.numel(), dtype=torch.float32, device="cuda")
-    _check("mbr_mlp_forward", lib().mbr_mlp_forward(_dptr(params), _dptr(q), q.numel(), _dptr(out),
-                                                    _stream(stream)))
+    n = q.numel()
+    _check("mbr_mlp_forward", lib().mbr_mlp_forward(_dvec(params, 4, 6337, "params"), _dvec(q, 4, n, "q"), n,
+                                                    _dvec(out, 4, n, "out"), _stream(stream)))
     return out
 
 
@@ -384,9 +402,10 @@ def mlp_gradients(params, q, target, stream=None):
     torch = _torch()
     grad = torch.empty(6337, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    _check("mbr_mlp_gradients", lib().mbr_mlp_gradients(_dptr(params), _dptr(q), _dptr(target),
-                                                        q.numel(), _dptr(grad), _dptr(loss),
-                                                        _stream(stream)))
+    n = q.numel()
+    _check("mbr_mlp_gradients", lib().mbr_mlp_gradients(_dvec(params, 4, 6337, "params"), _dvec(q, 4, n, "q"),
+                                                        _dvec(target, 4, n, "target"), n, _dptr(grad),
+                                                        _dptr(loss), _stream(stream)))
     return grad, loss
 
 
@@ -396,8 +415,9 @@ def rank_batch(ranker: Ranker, q, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty(q.numel(), dtype=torch.int32, device="cuda")
-    _check("mbr_rank_batch", lib().mbr_rank_batch(ranker.handle, _dptr(q), q.numel(), _dptr(out),
-                                                  _stream(stream)))
+    n = q.numel()
+    _check("mbr_rank_batch", lib().mbr_rank_batch(ranker.handle, _dvec(q, ranker.info().width_bits // 8, n, "q"),
+                                                  n, _dvec(out, 4, n, "out"), _stream(stream)))
     return out
 
 
@@ -407,8 +427,10 @@ def rank_batch64(ranker: Ranker, q, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty(q.numel(), dtype=torch.int64, device="cuda")
-    _check("mbr_rank_batch64", lib().mbr_rank_batch64(ranker.handle, _dptr(q), q.numel(), _dptr(out),
-                                                      _stream(stream)))
+    n = q.numel()
+    _check("mbr_rank_batch64", lib().mbr_rank_batch64(ranker.handle,
+                                                      _dvec(q, ranker.info().width_bits // 8, n, "q"), n,
+                                                      _dvec(out, 8, n, "out"), _stream(stream)))
     return out
 
 
@@ -462,7 +484,8 @@ def operator_create(sector: Sector, ranker: Ranker, terms, stream=None) -> Opera
 
 
 def operator_apply(op: Operator, x, y, stream=None):
-    _check("mbr_operator_apply", lib().mbr_operator_apply(op.handle, _dptr(x), _dptr(y), _stream(stream)))
+    _check("mbr_operator_apply", lib().mbr_operator_apply(op.handle, _dvec(x, 8, op.dim, "x"),
+                                                          _dvec(y, 8, op.dim, "y"), _stream(stream)))
     return y
 
 
@@ -472,7 +495,8 @@ def operator_lanczos(op: Operator, v0, nsteps: int, tol: float = 1e-12, stream=N
     nd = C.c_int32()
     al = np.zeros(nsteps)
     be = np.zeros(nsteps)
-    _check("mbr_operator_lanczos", lib().mbr_operator_lanczos(op.handle, _dptr(v0), nsteps, tol, C.byref(e0),
+    _check("mbr_operator_lanczos", lib().mbr_operator_lanczos(op.handle, _dvec(v0, 8, op.dim, "v0"), nsteps,
+                                                              tol, C.byref(e0),
                                                               C.byref(nd), C.c_void_p(al.ctypes.data),
                                                               C.c_void_p(be.ctypes.data), _stream(stream)))
     return float(e0.value), int(nd.value), al, be
@@ -515,7 +539,9 @@ def hubbard_create(L: int, bonds, sectors, U=None, eps=None, precision: int = F6
 
 
 def hubbard_apply(h: Hubbard, x, y, stream=None):
-    _check("mbr_hubbard_apply", lib().mbr_hubbard_apply(h.handle, _dptr(x), _dptr(y), _stream(stream)))
+    tsz = 8 if h.precision == F64 else 4
+    _check("mbr_hubbard_apply", lib().mbr_hubbard_apply(h.handle, _dvec(x, tsz, h.dim, "x"),
+                                                        _dvec(y, tsz, h.dim, "y"), _stream(stream)))
     return y
 
 
@@ -562,7 +588,8 @@ def lanczos_create(h: Hubbard, max_steps: int, reorth: bool = False, batched: bo
 
 
 def lanczos_start(lz: Lanczos, v0, stream=None):
-    _check("mbr_lanczos_start", lib().mbr_lanczos_start(lz.handle, _dptr(v0), _stream(stream)))
+    _check("mbr_lanczos_start", lib().mbr_lanczos_start(lz.handle, _dvec(v0, 8, lz.ham.dim, "v0"),
+                                                        _stream(stream)))
 
 
 def lanczos_step(lz: Lanczos, nsteps: int, stream=None):
@@ -594,8 +621,10 @@ def tridiag_lowest(alpha, beta, lengths, ld: int, out=None, stream=None):
     nb = lengths.numel()
     if out is None:
         out = torch.empty(nb, dtype=torch.float64, device="cuda")
-    _check("mbr_tridiag_lowest", lib().mbr_tridiag_lowest(_dptr(alpha), _dptr(beta), _dptr(lengths),
-                                                          ld, nb, _dptr(out), _stream(stream)))
+    _check("mbr_tridiag_lowest", lib().mbr_tridiag_lowest(_dvec(alpha, 8, nb * ld, "alpha"),
+                                                          _dvec(beta, 8, nb * ld, "beta"),
+                                                          _dvec(lengths, 4, nb, "lengths"), ld, nb,
+                                                          _dvec(out, 8, nb, "out"), _stream(stream)))
     return out
 
 

@@ -258,3 +258,27 @@ def test_unrank_spin_ragged_and_unaligned(L, nu, nd, qoff, ooff, n):
     inside = idx < st.size
     assert np.array_equal(got[inside], st[idx[inside]])
     assert (got[~inside] == ones).all()
+
+
+def test_binding_rejects_wrong_buffers():
+    """The C ABI takes raw pointers; the binding checks element size, device
+    and length before any launch."""
+    import torch
+    r = mbr.build_staggered_tables(12, 6, 6)
+    q = dev_u32(np.arange(100, dtype=np.uint64))
+    with pytest.raises(ValueError):
+        mbr.rank_batch(r, q.long())                                   # 8-byte queries for a 32-bit ranker
+    with pytest.raises(ValueError):
+        mbr.rank_batch(r, q, out=torch.empty(99, dtype=torch.int32, device="cuda"))   # short output
+    with pytest.raises(ValueError):
+        mbr.rank_batch(r, q.cpu())                                    # host tensor
+    s = mbr.sector_build(12, OC.constraints(12, 6))
+    with pytest.raises(ValueError):
+        mbr.unrank_batch(s, q, out=torch.empty(100, dtype=torch.int64, device="cuda"))
+    h = mbr.hubbard_create(4, [(0, 1, 1.0), (1, 2, 1.0)], [(2, 2)], U=[1.0] * 4)
+    x = torch.zeros(h.dim, dtype=torch.float32, device="cuda")      # fp64 Hamiltonian
+    with pytest.raises(ValueError):
+        mbr.hubbard_apply(h, x, torch.empty_like(x))
+    x = torch.zeros(h.dim - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        mbr.hubbard_apply(h, x, torch.zeros(h.dim, dtype=torch.float64, device="cuda"))
