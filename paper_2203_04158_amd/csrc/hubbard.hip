@@ -173,18 +173,6 @@ __device__ __forceinline__ T lz_out(T hx, T c1, T c2, T pv, bool has_p) {
     return has_p ? fma_t(-c2, pv, u) : u;
 }
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double s = 0;
-    if (threadIdx.x == 0)
-        for (int j = 0; j < (int)(blockDim.x >> 6); ++j) s += red[j];
-    return s;
-}
-
 template <class T>
 struct UpLists {
     const uint32_t *tgt;
@@ -325,10 +313,25 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
         t_end = a.n_tiles;
         t_step = gridDim.x;
     }
+    // A tile's partial of <q_j, u>: each wave leaves its sum in red, and wave 0
+    // adds them (a fixed tree) right after the next barrier, so the partial
+    // costs no barrier of its own.  red is written again only after the
+    // barrier that follows that fold.
+    bool pend = false;
+    uint32_t pend_slot = 0;
+    auto fold = [&]() {
+        if (threadIdx.x < 64) {
+            double v = threadIdx.x < (blockDim.x >> 6) ? red[threadIdx.x] : 0.0;
+            for (int o = 8; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (threadIdx.x == 0) a.ep.partial[pend_slot] = v;
+        }
+        pend = false;
+    };
     for (uint32_t ti = t_begin; ti < t_end; ti += t_step) {
         const HvTile tl = a.tiles[ti];
         const HvSector sc = a.secs[tl.sector];
         __syncthreads();  // LDS from the previous tile (and the table copy) settled
+        if (pend) fold();
         if (a.ep.active && !a.ep.active[tl.sector]) {
             if (a.ep.partial && threadIdx.x == 0) a.ep.partial[tl.slot] = 0.0;
             continue;
@@ -424,9 +427,16 @@ __global__ void __launch_bounds__(512) hv_kernel(HvArgs a) {
             }
         }
         if (a.ep.partial) {
-            double s = block_sum(dot, red);
-            if (threadIdx.x == 0) a.ep.partial[tl.slot] = s;
+            double v = dot;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+            pend = true;
+            pend_slot = tl.slot;
         }
+    }
+    if (pend) {
+        __syncthreads();
+        fold();
     }
 }
 
