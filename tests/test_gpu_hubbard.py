@@ -347,6 +347,32 @@ def test_autotune_cache_roundtrip_and_corrupt_entries(tmp_path, monkeypatch):
     assert len(cache.read_text().splitlines()) == 3  # served from the cache
 
 
+@pytest.mark.parametrize("G,block", [(1, 256), (2, 512), (4, 256)])
+@pytest.mark.parametrize("reorth", [False, True])
+def test_lanczos_on_tile_kernel_launch_shapes(G, block, reorth):
+    """Lanczos through the tile kernel's epilogue (G > 0): energies against
+    the oracle's sectors; batched launches bitwise equal to per-sector ones on
+    the same tiles (plain path), or equal to rounding where the batched
+    Gram-Schmidt passes merge tiles into larger groups."""
+    L, U = 8, 2.0
+    sectors = [(4, 4), (3, 5), (2, 2), (8, 0), (1, 0)]
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), sectors, U=[U] * L)
+    mbr.hubbard_set_config(h, 4, G, block)
+    r1 = _run_lanczos(h, 120, seed=9, reorth=reorth, batched=True)
+    r2 = _run_lanczos(h, 120, seed=9, reorth=reorth, batched=False)
+    if reorth:
+        assert np.allclose(r1[2][:, :10], r2[2][:, :10], rtol=0, atol=1e-10)
+        assert np.allclose(r1[3][:, :10], r2[3][:, :10], rtol=0, atol=1e-10)
+    else:
+        assert np.array_equal(r1[2], r2[2]) and np.array_equal(r1[3], r2[3])
+    tl = OH.terms(L, OH.chain_bonds(L), U)
+    for si, (nu, nd) in enumerate(sectors):
+        st = OH.sector(L, nu, nd)
+        exact = OL.lowest_eigenvalue(OH.sparse(st, tl))
+        assert abs(r2[0][si] - exact) <= 1e-9 * max(1.0, abs(exact))
+        assert abs(r1[0][si] - exact) <= 1e-9 * max(1.0, abs(exact)), (G, block, nu, nd, r1[0][si], exact)
+
+
 def test_lanczos_rejects_stale_launch_shape():
     L = 6
     h = mbr.hubbard_create(L, OH.chain_bonds(L), [(3, 3)], U=[4.0] * L)
