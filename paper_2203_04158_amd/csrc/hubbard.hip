@@ -819,6 +819,18 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     }
     __syncthreads();
 
+    // One alpha_up block per tile: the spin-down side of a row slot (its
+    // down-hop list, half state and energy) is the same in every tile of a
+    // sector, so a lane keeps its slots' copies in registers until the tile's
+    // sector changes, where registers allow: at most 32 list words, and in
+    // fp64 only the short lists of uniform hopping and at most two slots (the
+    // other fp64 shapes already fill the 128 registers of a 1024-lane
+    // workgroup).
+    constexpr bool kKeepDn = R * kWords <= 32 && (sizeof(T) == 4 || (UT && R <= 2));
+    uint32_t hlc[kKeepDn ? R : 1][kWords], gac[kKeepDn ? R : 1];
+    T gec[kKeepDn ? R : 1];
+    uint32_t kept_loff = 0xFFFFFFFFu, kept_hs = 0xFFFFFFFFu;
+
     for (int buf = 0; t_cur < t_end; t_cur += t_step, buf ^= 1) {
         const RowsTile c = rows_desc_uniform(qc);
         const uint32_t t_next = t_cur + t_step;
@@ -879,14 +891,30 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 // hops past nu read row 0 of the sector with coefficient 0), so
                 // the wait for slot r leaves slot r + 1 in flight
                 const T *pp = has_p ? p : x;
+                if constexpr (kKeepDn) {
+                    if (c.loff != kept_loff || c.hs_dn != kept_hs) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int rd = tid + r * kRowsBlock;
+                            const int rc = rd < (int)cdn ? rd : 0;
+                            rows_load_list(slists + (size_t)rc * kWords, hlc[r]);
+                            gac[r] = a.hs_states[c.hs_dn + rc];
+                            gec[r] = (T)a.hs_energy[c.hs_dn + rc];
+                        }
+                        kept_loff = c.loff;
+                        kept_hs = c.hs_dn;
+                    }
+                }
                 auto gather = [&](int r, int s) {
                     const int rd = tid + r * kRowsBlock;
                     const int rc = rd < (int)cdn ? rd : 0;
 #pragma unroll
                     for (int h = 0; h < kUpMax; ++h) gx[s][h] = src[h][rc];
-                    rows_load_list(slists + (size_t)rc * kWords, hl[s]);
-                    ga[s] = a.hs_states[c.hs_dn + rc];
-                    ge[s] = (T)a.hs_energy[c.hs_dn + rc];
+                    if constexpr (!kKeepDn) {
+                        rows_load_list(slists + (size_t)rc * kWords, hl[s]);
+                        ga[s] = a.hs_states[c.hs_dn + rc];
+                        ge[s] = (T)a.hs_energy[c.hs_dn + rc];
+                    }
                     if constexpr (LZ) gp_[s] = pp[base + rc];
                 };
                 gather(0, 0);
@@ -895,10 +923,13 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                     const int s = r & 1;
                     if (r + 1 < R) gather(r + 1, s ^ 1);
                     const int rd = tid + r * kRowsBlock;
-                    const T acc = rows_down<T, UT>(hl[s], bb, amp, rd < (int)cdn);
+                    const uint32_t(&hlr)[kWords] = kKeepDn ? hlc[kKeepDn ? r : 0] : hl[s];
+                    const uint32_t gar = kKeepDn ? gac[kKeepDn ? r : 0] : ga[s];
+                    const T ger = kKeepDn ? gec[kKeepDn ? r : 0] : ge[s];
+                    const T acc = rows_down<T, UT>(hlr, bb, amp, rd < (int)cdn);
                     if (rd < (int)cdn) {
                         const T xv = reinterpret_cast<const T *>(bb)[rd];
-                        const T dg = eu + ge[s] + rows_u_energy<T>(au & ga[s], a, ul);
+                        const T dg = eu + ger + rows_u_energy<T>(au & gar, a, ul);
                         T v = fma_t(dg, xv, UT ? tu * acc : acc);
                         // cf = 0 and gx = x[row 0] past nu: those terms add an exact zero
 #pragma unroll
