@@ -827,8 +827,9 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     // other fp64 shapes already fill the 128 registers of a 1024-lane
     // workgroup).
     constexpr bool kKeepDn = R * kWords <= 32 && (sizeof(T) == 4 || (UT && R <= 2));
-    uint32_t hlc[kKeepDn ? R : 1][kWords], gac[kKeepDn ? R : 1];
-    T gec[kKeepDn ? R : 1];
+    constexpr bool kKeepHs = kKeepDn || UT;  // the half states and energies alone
+    uint32_t hlc[kKeepDn ? R : 1][kWords], gac[kKeepHs ? R : 1];
+    T gec[kKeepHs ? R : 1];
     uint32_t kept_loff = 0xFFFFFFFFu, kept_hs = 0xFFFFFFFFu;
 
     for (int buf = 0; t_cur < t_end; t_cur += t_step, buf ^= 1) {
@@ -891,13 +892,13 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 // hops past nu read row 0 of the sector with coefficient 0), so
                 // the wait for slot r leaves slot r + 1 in flight
                 const T *pp = has_p ? p : x;
-                if constexpr (kKeepDn) {
+                if constexpr (kKeepHs) {
                     if (c.loff != kept_loff || c.hs_dn != kept_hs) {
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int rd = tid + r * kRowsBlock;
                             const int rc = rd < (int)cdn ? rd : 0;
-                            rows_load_list(slists + (size_t)rc * kWords, hlc[r]);
+                            if constexpr (kKeepDn) rows_load_list(slists + (size_t)rc * kWords, hlc[r]);
                             gac[r] = a.hs_states[c.hs_dn + rc];
                             gec[r] = (T)a.hs_energy[c.hs_dn + rc];
                         }
@@ -910,8 +911,8 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                     const int rc = rd < (int)cdn ? rd : 0;
 #pragma unroll
                     for (int h = 0; h < kUpMax; ++h) gx[s][h] = src[h][rc];
-                    if constexpr (!kKeepDn) {
-                        rows_load_list(slists + (size_t)rc * kWords, hl[s]);
+                    if constexpr (!kKeepDn) rows_load_list(slists + (size_t)rc * kWords, hl[s]);
+                    if constexpr (!kKeepHs) {
                         ga[s] = a.hs_states[c.hs_dn + rc];
                         ge[s] = (T)a.hs_energy[c.hs_dn + rc];
                     }
@@ -924,8 +925,8 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                     if (r + 1 < R) gather(r + 1, s ^ 1);
                     const int rd = tid + r * kRowsBlock;
                     const uint32_t(&hlr)[kWords] = kKeepDn ? hlc[kKeepDn ? r : 0] : hl[s];
-                    const uint32_t gar = kKeepDn ? gac[kKeepDn ? r : 0] : ga[s];
-                    const T ger = kKeepDn ? gec[kKeepDn ? r : 0] : ge[s];
+                    const uint32_t gar = kKeepHs ? gac[kKeepHs ? r : 0] : ga[s];
+                    const T ger = kKeepHs ? gec[kKeepHs ? r : 0] : ge[s];
                     const T acc = rows_down<T, UT>(hlr, bb, amp, rd < (int)cdn);
                     if (rd < (int)cdn) {
                         const T xv = reinterpret_cast<const T *>(bb)[rd];
