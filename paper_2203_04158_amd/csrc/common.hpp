@@ -116,6 +116,7 @@ struct mbr_sector {
     int device = 0;
     std::vector<mbr_popc_cons> cons;
     int32_t modulus = 0, residue = 0;  // modular weight constraint (modulus 0: none)
+    std::vector<int32_t> weights;      // orbital weights mod modulus (modulus > 0)
     mbr::DevBuf states;
 };
 

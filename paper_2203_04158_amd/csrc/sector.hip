@@ -207,6 +207,7 @@ mbr_status sector_build_impl(int32_t M, int32_t width_bits, int32_t n_cons, cons
     sec->cons = cv;
     sec->modulus = modulus;
     sec->residue = residue;
+    for (int i = 0; i < M && modulus > 0; ++i) sec->weights.push_back(cs.weight[i]);
     MBR_HIP(hipGetDevice(&sec->device));
     mbr_status st = sec->states.alloc(total * (width_bits / 8));
     if (st == MBR_OK) st = upload(d_off, off.data(), nruns * sizeof(uint64_t), s);

@@ -104,6 +104,7 @@ struct OpArgs {
     int64_t nt;
     const double *v;
     const P *m, *l, *x, *s;
+    const uint32_t *keep;  // per tuple: every member's target is a member
     const double *xin;
     double *out;
     StagArgs stag;
@@ -132,9 +133,17 @@ __global__ void __launch_bounds__(kBlock) op_apply_kernel(OpArgs<P> a) {
             if (a.x[t] == 0) {
                 rr = row;
             } else if constexpr (RK == kTrie) {
-                const uint32_t q = trie_rank_one<P>(be, a.trie);
-                if (q == MBR_NOT_FOUND) continue;  // the term leaves the sector
-                rr = q;
+                if (a.keep[t]) {
+                    // the target is a member, so the walk alone gives its rank
+                    uint32_t node = 0;
+                    for (int lv = 0; lv < a.trie.H; ++lv)
+                        node = a.trie.tab[a.trie.off[lv] + node + ((uint32_t)(be >> a.trie.shift[lv]) & a.trie.wmask[lv])];
+                    rr = node;
+                } else {
+                    const uint32_t q = trie_rank_one<P>(be, a.trie);
+                    if (q == MBR_NOT_FOUND) continue;  // the term leaves the sector
+                    rr = q;
+                }
             } else {
                 const int h = (sizeof(P) == 8) ? __popcll((uint64_t)be) : __popc((uint32_t)be);
                 if (h != a.stag.N || !below_width(be, a.stag.M)) continue;  // leaves C^M_N
@@ -252,7 +261,7 @@ struct mbr_operator {
     const mbr_ranker *rk = nullptr;
     int64_t nt = 0;
     int32_t M = 0, width_bits = 32;
-    mbr::DevBuf v, m, l, x, s;
+    mbr::DevBuf v, m, l, x, s, keep;
     int device = 0;
 };
 
@@ -281,6 +290,7 @@ mbr_status apply_t(const mbr_operator *op, const double *x, double *y, hipStream
     a.l = op->l.as<P>();
     a.x = op->x.as<P>();
     a.s = op->s.as<P>();
+    a.keep = op->keep.as<uint32_t>();
     a.xin = x;
     a.out = y;
     const mbr_ranker *r = op->rk;
@@ -392,7 +402,25 @@ mbr_status mbr_operator_create(const mbr_sector *sec, const mbr_ranker *rk, cons
         f[2][i] = terms[i].x;
         f[3][i] = terms[i].s;
     }
+    // A tuple keeps the sector when it moves no particle into or out of any
+    // constraint's orbitals and leaves the modular weight unchanged: the
+    // target of every member is then a member (bits outside m are untouched,
+    // and inside m the row holds l and the target l ^ x).
+    std::vector<uint32_t> keep(n, 0u);
+    for (int64_t i = 0; i < n_terms; ++i) {
+        const uint64_t lo = terms[i].l, hi = terms[i].l ^ terms[i].x;
+        bool k = true;
+        for (const mbr_popc_cons &c : sec->cons)
+            k = k && __builtin_popcountll(lo & c.mask) == __builtin_popcountll(hi & c.mask);
+        if (sec->modulus > 0) {
+            int64_t dw = 0;
+            for (int b = 0; b < sec->M; ++b) dw += (int64_t)(((hi >> b) & 1) - ((lo >> b) & 1)) * sec->weights[b];
+            k = k && dw % sec->modulus == 0;
+        }
+        keep[i] = k ? 1u : 0u;
+    }
     hipStream_t st = as_stream(stream);
+    MBR_TRY(upload(op->keep, keep.data(), n * 4, st));
     MBR_TRY(upload(op->v, v.data(), n * 8, st));
     DevBuf *dst[4] = {&op->m, &op->l, &op->x, &op->s};
     for (int k = 0; k < 4; ++k) {
