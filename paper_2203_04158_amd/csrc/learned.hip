@@ -6,9 +6,13 @@
 //  * stage 2: y selects one of n_leaves = 2^b leaves, leaf floor(y 2^b); each
 //    leaf records the smallest and largest rank of the members the network
 //    sends to it, measured with the query kernel's own arithmetic.
-// A query is answered by bisection in states[lo .. hi] of its leaf, so answers
-// are exact: a member always lies inside its leaf's window and a non-member is
-// never found.  The recorded error e is the widest leaf window (hi - lo); when
+// A query is answered by the lower bound of the pattern in states[lo .. hi] of
+// its leaf, so answers are exact: a member always lies inside its leaf's window
+// and a non-member is never found.  The lower bound is found level by level:
+// a bisection over every kSample^2-th state (a copy the caches hold), then one
+// over the at most kSample entries of every kSample-th state that it leaves
+// open, then one inside a block of kSample states (64 bytes), so the probes of
+// the two large arrays cost about one line each per query.  The recorded error e is the widest leaf window (hi - lo); when
 // e exceeds the caller's bound the fallback ranker answers instead.  The
 // single-window error max |rint(N_s y) - i| of stage 1 alone is kept as a
 // statistic.
@@ -263,8 +267,36 @@ __global__ void __launch_bounds__(256) leaf_stats_kernel(const uint16_t *__restr
     }
 }
 
+constexpr uint32_t kSample = 16;  // states per sampled block (64 bytes)
+
+// sample[b] = states[b stride], b < nb
+__global__ void sample_kernel(const uint32_t *__restrict__ states, uint32_t stride,
+                              uint32_t *__restrict__ sample, uint64_t nb) {
+    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x)
+        sample[b] = states[b * stride];
+}
+
+// Narrow [L, H1), which holds the lower bound of a among the states of the
+// window (H1 when none is >= a), to the blocks of `stride` states: among the
+// blocks b with b stride in (L, H1 - 1], the first whose sampled state is not
+// below a bounds the answer from above and the block before it from below.
+__device__ __forceinline__ void narrow(const uint32_t *__restrict__ smp, uint32_t stride, uint32_t a,
+                                       uint32_t &L, uint32_t &H1) {
+    uint32_t bl = L / stride + 1, br = (H1 - 1) / stride + 1;
+    while (bl < br) {
+        const uint32_t mid = bl + ((br - bl) >> 1);
+        if (smp[mid] < a) bl = mid + 1;
+        else br = mid;
+    }
+    const uint32_t lo = (bl - 1) * stride, hi = bl * stride;
+    L = lo > L ? lo : L;
+    H1 = hi < H1 ? hi : H1;
+}
+
 __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__restrict__ wb,
                                                            const uint32_t *__restrict__ states,
+                                                           const uint32_t *__restrict__ sample,
+                                                           const uint32_t *__restrict__ sample2,
                                                            const uint2 *__restrict__ leaf, uint32_t nleaf,
                                                            int M, const uint32_t *__restrict__ q,
                                                            uint64_t nq, uint32_t *__restrict__ out) {
@@ -283,6 +315,8 @@ __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__res
         uint32_t L = w.x, R = w.y + 1u;
         bool hit = false;
         if (in_width && w.x <= w.y) {
+            narrow(sample2, kSample * kSample, a, L, R);
+            narrow(sample, kSample, a, L, R);
             while (L < R) {
                 const uint32_t mid = L + ((R - L) >> 1);
                 if (states[mid] < a) L = mid + 1;
@@ -530,6 +564,7 @@ struct LearnedModel {
     int32_t M = 0;
     mbr::DevBuf w, m, v, wr, wb;  // masters, Adam moments, rounded fp32, bf16
     mbr::DevBuf leaf;             // stage-2 windows, uint2 {lo, hi} per leaf
+    mbr::DevBuf sample, sample2;  // every kSample-th and kSample^2-th state of the sector
     uint32_t n_leaves = 0;
     uint64_t e = 0;               // widest leaf window, hi - lo
     uint64_t e_single = 0;        // max |rint(N_s y) - i| of stage 1 alone
@@ -539,7 +574,9 @@ struct LearnedModel {
 };
 
 void learned_free(LearnedModel *m) { delete m; }
-uint64_t learned_bytes(const LearnedModel *m) { return m ? (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8 : 0; }
+uint64_t learned_bytes(const LearnedModel *m) {
+    return m ? (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8 + m->sample.bytes + m->sample2.bytes : 0;
+}
 
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                hipStream_t s) {
@@ -550,7 +587,8 @@ mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, u
     }
     const unsigned grid = mbr::grid_for(n, 256, mbr::device_cu_count() * 8);
     learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(),
-                                             lm.leaf.as<uint2>(), lm.n_leaves, lm.M,
+                                             lm.sample.as<uint32_t>(), lm.sample2.as<uint32_t>(), lm.leaf.as<uint2>(),
+                                             lm.n_leaves, lm.M,
                                              static_cast<const uint32_t *>(q), n, out);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
@@ -638,6 +676,14 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
     while (nl < sec->n / 4 && nl < (1ull << 26)) nl <<= 1;
     lm->n_leaves = (uint32_t)nl;
     MBR_TRY(lm->leaf.alloc(nl * 8));
+    const uint64_t nsb = (sec->n + kSample - 1) / kSample;
+    const uint64_t nsb2 = (sec->n + kSample * kSample - 1) / (kSample * kSample);
+    MBR_TRY(lm->sample.alloc(nsb * 4));
+    MBR_TRY(lm->sample2.alloc(nsb2 * 4));
+    sample_kernel<<<grid_for(nsb, 256, device_cu_count() * 8), 256, 0, s>>>(sec->states.as<uint32_t>(), kSample,
+                                                                              lm->sample.as<uint32_t>(), nsb);
+    sample_kernel<<<grid_for(nsb2, 256, device_cu_count() * 8), 256, 0, s>>>(
+        sec->states.as<uint32_t>(), kSample * kSample, lm->sample2.as<uint32_t>(), nsb2);
     leaf_clear_kernel<<<(unsigned)((nl + 255) / 256), 256, 0, s>>>(lm->leaf.as<uint2>(), (uint32_t)nl);
     leaf_build_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
                                            (uint32_t)nl, lm->leaf.as<uint2>());
