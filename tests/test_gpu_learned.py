@@ -195,3 +195,18 @@ def test_learned_chain_sector_full_size():
     noise = synth.splitmix64(78, 1 << 20) & np.uint64((1 << 28) - 1)
     q = np.concatenate([noise, st[synth.uniform_indices(79, 1 << 20, st.size)]])
     assert np.array_equal(host_rank(mbr.rank_batch(lr_, dev_u32(q))), OC.bisect_rank(st, q))
+
+
+@pytest.mark.parametrize("M,N", [(17, 1), (10, 4), (11, 4), (12, 5), (16, 3)])
+def test_learned_ranks_exact_on_small_and_ragged_sectors(M, N):
+    """Sector sizes 17, 210, 330, 792 and 560: not multiples of the 16- and
+    256-state sampling strides, windows that start and end anywhere; every
+    member and random non-members against the oracle."""
+    cons = OC.constraints(M, N)
+    st = OC.sector_enumerate(M, cons)
+    s, trie, lr_ = _learned(M, cons, epochs=4, batch=256)
+    got = host_rank(mbr.rank_batch(lr_, dev_u32(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    noise = synth.splitmix64(M * 7 + N, 20000) & np.uint64((1 << (M + 1)) - 1)
+    got = host_rank(mbr.rank_batch(lr_, dev_u32(noise)))
+    assert np.array_equal(got, OC.bisect_rank(st, noise))
