@@ -63,9 +63,9 @@ struct MlpFrags {
     bf16x4 w1[4][2];
     bf16x4 w2[4][4];
     bf16x4 w3[4];
-    float b1[4][4];
-    float b2[4][4];
-    float b3;
+    f32x4 b1[4];  // the accumulators start from the biases
+    f32x4 b2[4];
+    f32x4 b3;
 };
 
 // wb: bf16 weights in parameter order.
@@ -95,17 +95,28 @@ __device__ __forceinline__ void load_frags(MlpFrags &f, const uint16_t *__restri
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             f.w3[ks][j] = row == 0 ? (short)wb[P_W3 + 16 * ks + kg + j] : (short)0;
-    f.b3 = bf2f(wb[P_B3]);
+    const float b3 = bf2f(wb[P_B3]);
+    f.b3 = (f32x4){b3, b3, b3, b3};
 }
 
-__device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc, const float *bias) {
-    bf16x4 o;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float v = acc[r] + bias[r];
-        o[r] = (short)f2bf(v > 0.f ? v : 0.f);
-    }
-    return o;
+// ReLU(acc) rounded to bf16 (nearest even, the rounding of f2bf for finite
+// values) by the hardware conversion, two values per instruction; acc
+// already holds the bias.  The ReLU is an integer maximum with 0 on the bit
+// patterns: every negative float (and -0) has the sign bit set.
+typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float relu_f(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, b > 0 ? b : 0);
+}
+
+__device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc) {
+    u32x2 w;
+    w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){relu_f(acc[0]), relu_f(acc[1])}, bf16v2));
+    w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){relu_f(acc[2]), relu_f(acc[3])}, bf16v2));
+    return __builtin_bit_cast(bf16x4, w);
 }
 
 // Network output for the 16 queries held by lanes 16*grp .. 16*grp+15 of the
@@ -123,22 +134,22 @@ __device__ __forceinline__ float mlp16(const MlpFrags &f, uint32_t q, int grp) {
     bf16x4 h1[4], h2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc = f.b1[t];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[t][ks], xb[ks], acc, 0, 0, 0);
-        h1[t] = relu_bf16(acc, f.b1[t]);
+        h1[t] = relu_bf16(acc);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc = f.b2[t];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w2[t][ks], h1[ks], acc, 0, 0, 0);
-        h2[t] = relu_bf16(acc, f.b2[t]);
+        h2[t] = relu_bf16(acc);
     }
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc = f.b3;
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w3[ks], h2[ks], acc, 0, 0, 0);
-    return acc[0] + f.b3;
+    return acc[0];
 }
 
 // Network outputs for the 64 queries of a wave, each lane receiving its own.
