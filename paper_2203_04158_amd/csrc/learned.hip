@@ -8,11 +8,12 @@
 //    sends to it, measured with the query kernel's own arithmetic.
 // A query is answered by the lower bound of the pattern in states[lo .. hi] of
 // its leaf, so answers are exact: a member always lies inside its leaf's window
-// and a non-member is never found.  The lower bound is found level by level:
-// a bisection over every kSample^2-th state (a copy the caches hold), then one
-// over the at most kSample entries of every kSample-th state that it leaves
-// open, then one inside a block of kSample states (64 bytes), so the probes of
-// the two large arrays cost about one line each per query.  The recorded error e is the widest leaf window (hi - lo); when
+// and a non-member is never found.  The lower bound is found level by level
+// over copies of every kSample^l-th state, l = H..1: a bisection over the top
+// copy (at most kTopMax entries, staged in LDS), then at each level one over
+// the at most kSample entries the level above leaves open (one 64-byte line),
+// then one inside a block of kSample states, so below the top each level
+// costs one line per query.  The recorded error e is the widest leaf window (hi - lo); when
 // e exceeds the caller's bound the fallback ranker answers instead.  The
 // single-window error max |rint(N_s y) - i| of stage 1 alone is kept as a
 // statistic.
@@ -278,7 +279,15 @@ __global__ void __launch_bounds__(256) leaf_stats_kernel(const uint16_t *__restr
     }
 }
 
-constexpr uint32_t kSample = 16;  // states per sampled block (64 bytes)
+constexpr uint32_t kSample = 16;     // states per sampled block (64 bytes)
+constexpr uint32_t kTopMax = 8192;   // entries of the top copy (32 KB of LDS)
+constexpr int kMaxLevels = 8;        // kSample^8 = 2^32 states
+
+struct SampleLevels {
+    const uint32_t *lv[kMaxLevels];  // lv[l]: states[b kSample^(l+1)]
+    int32_t H;                       // copies; lv[H-1] is the top
+    uint32_t top_n;                  // entries of the top copy
+};
 
 // sample[b] = states[b stride], b < nb
 __global__ void sample_kernel(const uint32_t *__restrict__ states, uint32_t stride,
@@ -291,8 +300,8 @@ __global__ void sample_kernel(const uint32_t *__restrict__ states, uint32_t stri
 // window (H1 when none is >= a), to the blocks of `stride` states: among the
 // blocks b with b stride in (L, H1 - 1], the first whose sampled state is not
 // below a bounds the answer from above and the block before it from below.
-__device__ __forceinline__ void narrow(const uint32_t *__restrict__ smp, uint32_t stride, uint32_t a,
-                                       uint32_t &L, uint32_t &H1) {
+template <class PTR>
+__device__ __forceinline__ void narrow(PTR smp, uint32_t stride, uint32_t a, uint32_t &L, uint32_t &H1) {
     uint32_t bl = L / stride + 1, br = (H1 - 1) / stride + 1;
     while (bl < br) {
         const uint32_t mid = bl + ((br - bl) >> 1);
@@ -306,11 +315,13 @@ __device__ __forceinline__ void narrow(const uint32_t *__restrict__ smp, uint32_
 
 __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__restrict__ wb,
                                                            const uint32_t *__restrict__ states,
-                                                           const uint32_t *__restrict__ sample,
-                                                           const uint32_t *__restrict__ sample2,
+                                                           SampleLevels sl,
                                                            const uint2 *__restrict__ leaf, uint32_t nleaf,
                                                            int M, const uint32_t *__restrict__ q,
                                                            uint64_t nq, uint32_t *__restrict__ out) {
+    __shared__ uint32_t top[kTopMax];
+    for (uint32_t i = threadIdx.x; i < sl.top_n; i += blockDim.x) top[i] = sl.lv[sl.H - 1][i];
+    __syncthreads();
     MlpFrags f;
     load_frags(f, wb);
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -326,8 +337,13 @@ __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__res
         uint32_t L = w.x, R = w.y + 1u;
         bool hit = false;
         if (in_width && w.x <= w.y) {
-            narrow(sample2, kSample * kSample, a, L, R);
-            narrow(sample, kSample, a, L, R);
+            uint32_t stride = 1;
+            for (int l = 0; l < sl.H; ++l) stride *= kSample;
+            narrow(top, stride, a, L, R);
+            for (int l = sl.H - 2; l >= 0; --l) {
+                stride /= kSample;
+                narrow(sl.lv[l], stride, a, L, R);
+            }
             while (L < R) {
                 const uint32_t mid = L + ((R - L) >> 1);
                 if (states[mid] < a) L = mid + 1;
@@ -575,7 +591,8 @@ struct LearnedModel {
     int32_t M = 0;
     mbr::DevBuf w, m, v, wr, wb;  // masters, Adam moments, rounded fp32, bf16
     mbr::DevBuf leaf;             // stage-2 windows, uint2 {lo, hi} per leaf
-    mbr::DevBuf sample, sample2;  // every kSample-th and kSample^2-th state of the sector
+    mbr::DevBuf sample[kMaxLevels];  // copy l: every kSample^(l+1)-th state of the sector
+    int32_t n_sample = 0;
     uint32_t n_leaves = 0;
     uint64_t e = 0;               // widest leaf window, hi - lo
     uint64_t e_single = 0;        // max |rint(N_s y) - i| of stage 1 alone
@@ -586,7 +603,10 @@ struct LearnedModel {
 
 void learned_free(LearnedModel *m) { delete m; }
 uint64_t learned_bytes(const LearnedModel *m) {
-    return m ? (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8 + m->sample.bytes + m->sample2.bytes : 0;
+    if (!m) return 0;
+    uint64_t b = (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8;
+    for (int l = 0; l < m->n_sample; ++l) b += m->sample[l].bytes;
+    return b;
 }
 
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
@@ -597,9 +617,16 @@ mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, u
         return mbr_rank_batch(r->fallback, q, n, out, s);
     }
     const unsigned grid = mbr::grid_for(n, 256, mbr::device_cu_count() * 8);
-    learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(),
-                                             lm.sample.as<uint32_t>(), lm.sample2.as<uint32_t>(), lm.leaf.as<uint2>(),
-                                             lm.n_leaves, lm.M,
+    SampleLevels sl{};
+    sl.H = lm.n_sample;
+    uint64_t stride = 1;
+    for (int l = 0; l < lm.n_sample; ++l) {
+        sl.lv[l] = lm.sample[l].as<uint32_t>();
+        stride *= kSample;
+    }
+    sl.top_n = (uint32_t)((lm.n + stride - 1) / stride);
+    learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(), sl,
+                                             lm.leaf.as<uint2>(), lm.n_leaves, lm.M,
                                              static_cast<const uint32_t *>(q), n, out);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
@@ -687,14 +714,20 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
     while (nl < sec->n / 4 && nl < (1ull << 26)) nl <<= 1;
     lm->n_leaves = (uint32_t)nl;
     MBR_TRY(lm->leaf.alloc(nl * 8));
-    const uint64_t nsb = (sec->n + kSample - 1) / kSample;
-    const uint64_t nsb2 = (sec->n + kSample * kSample - 1) / (kSample * kSample);
-    MBR_TRY(lm->sample.alloc(nsb * 4));
-    MBR_TRY(lm->sample2.alloc(nsb2 * 4));
-    sample_kernel<<<grid_for(nsb, 256, device_cu_count() * 8), 256, 0, s>>>(sec->states.as<uint32_t>(), kSample,
-                                                                              lm->sample.as<uint32_t>(), nsb);
-    sample_kernel<<<grid_for(nsb2, 256, device_cu_count() * 8), 256, 0, s>>>(
-        sec->states.as<uint32_t>(), kSample * kSample, lm->sample2.as<uint32_t>(), nsb2);
+    // sampled copies, every kSample^l-th state, until the top one fits kTopMax
+    {
+        uint64_t stride = 1, nb = sec->n;
+        lm->n_sample = 0;
+        do {
+            stride *= kSample;
+            nb = (sec->n + stride - 1) / stride;
+            DevBuf &d = lm->sample[lm->n_sample++];
+            MBR_TRY(d.alloc(nb * 4));
+            sample_kernel<<<grid_for(nb, 256, device_cu_count() * 8), 256, 0, s>>>(
+                sec->states.as<uint32_t>(), (uint32_t)stride, d.as<uint32_t>(), nb);
+        } while (nb > kTopMax && lm->n_sample < kMaxLevels);
+        MBR_HIP(hipGetLastError());
+    }
     leaf_clear_kernel<<<(unsigned)((nl + 255) / 256), 256, 0, s>>>(lm->leaf.as<uint2>(), (uint32_t)nl);
     leaf_build_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
                                            (uint32_t)nl, lm->leaf.as<uint2>());
