@@ -287,13 +287,42 @@ struct SampleLevels {
     const uint32_t *lv[kMaxLevels];  // lv[l]: states[b kSample^(l+1)]
     int32_t H;                       // copies; lv[H-1] is the top
     uint32_t top_n;                  // entries of the top copy
+    uint64_t n;                      // states
 };
 
-// sample[b] = states[b stride], b < nb
+// sample[b] = states[b stride] for b < nb, all ones up to the padded length
+// npad (a multiple of kSample, so every aligned line of the copy can be read
+// whole).
 __global__ void sample_kernel(const uint32_t *__restrict__ states, uint32_t stride,
-                              uint32_t *__restrict__ sample, uint64_t nb) {
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x)
-        sample[b] = states[b * stride];
+                              uint32_t *__restrict__ sample, uint64_t nb, uint64_t npad) {
+    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < npad; b += (uint64_t)gridDim.x * blockDim.x)
+        sample[b] = b < nb ? states[b * stride] : 0xFFFFFFFFu;
+}
+
+// Entries [lo, hi) of v lie in the aligned line of kSample entries at base;
+// their lower bound for a is lo plus the number below a (they are sorted).
+// The line is read as four 16-byte loads in one round trip.
+__device__ __forceinline__ uint32_t line_lower_bound(const uint32_t *__restrict__ v, uint32_t base,
+                                                     uint32_t lo, uint32_t hi, uint32_t a) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(v + base);
+    const uint4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const uint32_t e[kSample] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                                 q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kSample; ++i) c += (base + i >= lo && base + i < hi && e[i] < a) ? 1u : 0u;
+    return lo + c;
+}
+
+// narrow() for a copy below the top: the blocks it considers are the at most
+// kSample children of the block the level above left open, one aligned line.
+__device__ __forceinline__ void narrow_line(const uint32_t *__restrict__ smp, uint32_t stride, uint32_t a,
+                                            uint32_t &L, uint32_t &H1) {
+    const uint32_t b0 = L / stride + 1, b1 = (H1 - 1) / stride + 1;
+    const uint32_t bl = b1 > b0 ? line_lower_bound(smp, (b0 - 1) & ~(kSample - 1), b0, b1, a) : b0;
+    const uint32_t lo = (bl - 1) * stride, hi = bl * stride;
+    L = lo > L ? lo : L;
+    H1 = hi < H1 ? hi : H1;
 }
 
 // Narrow [L, H1), which holds the lower bound of a among the states of the
@@ -342,12 +371,18 @@ __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__res
             narrow(top, stride, a, L, R);
             for (int l = sl.H - 2; l >= 0; --l) {
                 stride /= kSample;
-                narrow(sl.lv[l], stride, a, L, R);
+                narrow_line(sl.lv[l], stride, a, L, R);
             }
-            while (L < R) {
-                const uint32_t mid = L + ((R - L) >> 1);
-                if (states[mid] < a) L = mid + 1;
-                else R = mid;
+            // [L, R) lies in one aligned block of kSample states
+            const uint32_t base = L & ~(kSample - 1);
+            if ((uint64_t)base + kSample <= sl.n) {
+                L = line_lower_bound(states, base, L, R, a);
+            } else {
+                while (L < R) {
+                    const uint32_t mid = L + ((R - L) >> 1);
+                    if (states[mid] < a) L = mid + 1;
+                    else R = mid;
+                }
             }
             hit = L <= w.y && states[L] == a;
         }
@@ -625,6 +660,7 @@ mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, u
         stride *= kSample;
     }
     sl.top_n = (uint32_t)((lm.n + stride - 1) / stride);
+    sl.n = lm.n;
     learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(), sl,
                                              lm.leaf.as<uint2>(), lm.n_leaves, lm.M,
                                              static_cast<const uint32_t *>(q), n, out);
@@ -721,10 +757,11 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
         do {
             stride *= kSample;
             nb = (sec->n + stride - 1) / stride;
+            const uint64_t npad = (nb + kSample - 1) / kSample * kSample;
             DevBuf &d = lm->sample[lm->n_sample++];
-            MBR_TRY(d.alloc(nb * 4));
-            sample_kernel<<<grid_for(nb, 256, device_cu_count() * 8), 256, 0, s>>>(
-                sec->states.as<uint32_t>(), (uint32_t)stride, d.as<uint32_t>(), nb);
+            MBR_TRY(d.alloc(npad * 4));
+            sample_kernel<<<grid_for(npad, 256, device_cu_count() * 8), 256, 0, s>>>(
+                sec->states.as<uint32_t>(), (uint32_t)stride, d.as<uint32_t>(), nb, npad);
         } while (nb > kTopMax && lm->n_sample < kMaxLevels);
         MBR_HIP(hipGetLastError());
     }
