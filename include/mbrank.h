@@ -204,7 +204,9 @@ mbr_status mbr_trie_level_entries(const mbr_ranker *r, uint64_t *entries, int32_
  * Stage 2 has n_leaves = 2^b leaves (about one per four members); leaf
  * floor(y 2^b) records the smallest and largest rank of the members the
  * network sends to it, measured with the query kernel's own arithmetic.  A
- * query bisects states[lo..hi] of its leaf, so ranks are exact.  The recorded
+ * query takes the lower bound of its pattern in states[lo..hi] of its leaf
+ * (through sampled copies of every 16^l-th state, which the ranker holds on
+ * the device, about 1/15 of the list), so ranks are exact.  The recorded
  * error e is the widest leaf window hi - lo; when it exceeds opts->max_window,
  * `fallback` answers instead (the fallback must rank the same sector; the
  * learned ranker keeps a reference to it and to `s`).  width_bits must be 32.
