@@ -245,17 +245,17 @@ def row_unrank(torch, mbr, reps):
 
 def row_staggered64(torch, mbr, reps):
     """64-bit patterns and ranks: M = 64, N = 32 (C(64,32) = 1.83e18 states, no
-    list can hold them); 2^22 queries; with 8-byte entries the table fits LDS
-    at k = 4 (49 KB) but not at k = 8 (377 KB) or 16 (44 MB), which are read
-    through the caches.  Checked by agreement of the three tables and by the
-    range of the ranks."""
+    list can hold them); 2^22 queries; with 8-byte entries the rows members
+    reach fit LDS at k = 4 (35 KB) and k = 5 (56 KB) but not at k = 8
+    (278 KB) or 16 (40 MB), which are read through the caches.  Checked by
+    agreement of the four tables and by the range of the ranks."""
     import synth
     M, N, nq = 64, 32, 1 << 22
     base = synth.random_subset_patterns(64, 1 << 18, M, N)
     q = torch.from_numpy(np.tile(base, nq // base.size).view(np.int64)).cuda()
     res = {"workload": "M=64 N=32, 2^22 queries (2^18 distinct uniform 32-subsets), 64-bit ranks"}
     outs = {}
-    for k in (4, 8, 16):
+    for k in (4, 5, 8, 16):
         r = mbr.build_staggered_tables(M, N, k, width_bits=64)
         out = torch.empty(nq, dtype=torch.int64, device="cuda")
         ms = time_launches(torch, lambda: mbr.rank_batch64(r, q, out=out), reps)
@@ -265,7 +265,8 @@ def row_staggered64(torch, mbr, reps):
                         "table_bytes": int(r.info().bytes), "roofline": roof}
         del r
     ranks = outs[8].cpu().numpy().view(np.uint64)
-    res["exact"] = (bool(torch.equal(outs[4], outs[8])) and bool(torch.equal(outs[8], outs[16]))
+    res["exact"] = (bool(torch.equal(outs[4], outs[8])) and bool(torch.equal(outs[5], outs[8]))
+                    and bool(torch.equal(outs[8], outs[16]))
                     and bool((ranks < np.uint64(math.comb(M, N))).all()))
     return res
 

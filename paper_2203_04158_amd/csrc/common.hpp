@@ -128,6 +128,12 @@ struct StagTable {
     int32_t nrows = 0;
     mbr::DevBuf table;         // nrows << k entries
     std::vector<uint64_t> host; // same entries as uint64
+    // Fixed particle number N: only the rows a member can reach, N' in
+    // [max(0, N - (M - c k)), min(c k, N)] for chunk c; trim_rowoff[c] is the
+    // row of N' = 0 in that copy (negative when the first rows are cut).
+    mbr::DevBuf trim;
+    int32_t trim_rowoff[65] = {0};
+    uint64_t trim_entries = 0;
 };
 
 mbr_status stag_build(StagTable &t, int32_t M, int32_t k, int32_t nmax, int32_t entry_bytes,

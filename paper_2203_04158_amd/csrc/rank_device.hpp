@@ -7,8 +7,9 @@
 
 struct StagArgs {
     int32_t M, k, nch, N;
-    int32_t rowoff[16];
+    int32_t rowoff[16];  // row of (chunk c, N' = 0); may be negative for a trimmed table
     uint64_t nentries;
+    uint64_t safe;       // pattern ranked in place of a non-member (its rows exist)
 };
 
 template <class P>

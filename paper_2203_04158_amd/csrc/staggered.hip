@@ -61,6 +61,33 @@ mbr_status stag_build(StagTable &t, int32_t M, int32_t k, int32_t nmax, int32_t 
     return upload(t.table, v.data(), n * 2, stream);
 }
 
+// The rows of a fixed-N table that members reach (LDS copies of it are
+// smaller; the full table stays the reference layout).
+mbr_status stag_trim(StagTable &t, int32_t N, hipStream_t stream) {
+    using namespace mbr;
+    const uint64_t width = 1ull << t.k;
+    std::vector<uint64_t> h;
+    int rows = 0;
+    for (int c = 0; c < t.nch; ++c) {
+        const int Mp = c * t.k;
+        const int lo = N - (t.M - Mp) > 0 ? N - (t.M - Mp) : 0, hi = Mp < N ? Mp : N;
+        t.trim_rowoff[c] = rows - lo;
+        for (int Np = lo; Np <= hi; ++Np) {
+            const uint64_t *row = &t.host[(uint64_t)(t.rowoff[c] + Np) * width];
+            h.insert(h.end(), row, row + width);
+        }
+        rows += hi - lo + 1;
+    }
+    t.trim_entries = h.size();
+    if (t.entry_bytes == 8) return upload(t.trim, h.data(), h.size() * 8, stream);
+    if (t.entry_bytes == 4) {
+        std::vector<uint32_t> v(h.begin(), h.end());
+        return upload(t.trim, v.data(), v.size() * 4, stream);
+    }
+    std::vector<uint16_t> v(h.begin(), h.end());
+    return upload(t.trim, v.data(), v.size() * 2, stream);
+}
+
 namespace {
 
 // Smallest entry width (bytes) holding every partial rank of a table whose
@@ -126,7 +153,7 @@ template <class P, class E, class RT>
 __device__ __forceinline__ RT stag_query(P x, const E *tab, const StagArgs &a) {
     const int h = (sizeof(P) == 8) ? __popcll((uint64_t)x) : __popc((uint32_t)x);
     const bool ok = below_width(x, a.M) && (a.N < 0 || h == a.N);
-    const uint64_t r = stag_rank<P, E>(ok ? x : (P)0, tab, a);  // 0 keeps every row in range
+    const uint64_t r = stag_rank<P, E>(ok ? x : (P)a.safe, tab, a);  // a.safe: its rows are in the table
     return ok ? (RT)r : (RT)~(RT)0;
 }
 
@@ -282,15 +309,23 @@ bool vec_aligned(const void *q, const RT *out) {
 template <class P, class E, int V, class RT>
 mbr_status launch_stag_v(const mbr_ranker *r, const void *q, uint64_t n, RT *out, hipStream_t s) {
     StagArgs a = make_args(r->stag, r->N);
+    const E *tab = r->stag.table.as<E>();
+    if (r->stag.trim_entries) {
+        // fixed N: the trimmed rows, and the lowest member in place of a non-member
+        for (int c = 0; c < a.nch; ++c) a.rowoff[c] = r->stag.trim_rowoff[c];
+        a.nentries = r->stag.trim_entries;
+        a.safe = r->N >= 64 ? ~0ull : ((1ull << r->N) - 1);
+        tab = r->stag.trim.as<E>();
+    }
     size_t lds = a.nentries * sizeof(E);
     unsigned grid = mbr::grid_for((n + V - 1) / V, kBlock * kVecs, mbr::device_cu_count() * 8);
     if (lds <= kLdsTable) {
         auto kern = rank_staggered_kernel<P, E, true, V, RT>;
         MBR_TRY(set_lds(kern, lds));
-        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, r->stag.table.as<E>(), a);
+        kern<<<grid, kBlock, lds, s>>>(static_cast<const P *>(q), n, out, tab, a);
     } else {
         rank_staggered_kernel<P, E, false, V, RT><<<grid, kBlock, 0, s>>>(static_cast<const P *>(q), n, out,
-                                                                         r->stag.table.as<E>(), a);
+                                                                         tab, a);
     }
     MBR_HIP(hipGetLastError());
     return MBR_OK;
@@ -411,6 +446,7 @@ mbr_status mbr_build_staggered_tables(int32_t M, int32_t N, int32_t k, int32_t w
     if (((uint64_t)(nch * (nmax + 1)) << k) > (1ull << 26))
         MBR_FAIL_DEL(r, MBR_EUNSUPPORTED, "staggered table beyond 2^26 entries");
     mbr_status st = stag_build(r->stag, M, k, nmax, entry_bytes_for(M, nmax), as_stream(stream));
+    if (st == MBR_OK && N >= 0) st = stag_trim(r->stag, N, as_stream(stream));
     if (st != MBR_OK) {
         delete r;
         return st;
