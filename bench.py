@@ -16,9 +16,10 @@ checked for exactness or against stored oracle energies):
   staggered64  M=64, N=32 with 64-bit patterns and ranks; 2^22 queries; k = 4, 8, 16
   trie       M=32, N=16 with >= 6 of orbitals 0-7 occupied (66,110,671 states);
              2^24 queries, 90% members and 10% non-members; k = 4 and 8
-  learned    learned index vs trie vs spin-product staggered rank on the
-             (7,7) chain sector as 28-bit patterns, and learned vs trie on
-             M = 32 with 8 + 8 particles (165,636,900 states); 2^24 queries
+  learned    learned index vs its search without the network vs trie vs
+             spin-product staggered rank on the (7,7) chain sector as 28-bit
+             patterns, and the first three on M = 32 with 8 + 8 particles
+             (165,636,900 states); 2^24 queries
   batched    Anderson impurity model (12 sites, U = 8, eps_d = -4), all 169
              (N_up, N_dn) sectors, 150 steps with full reorthogonalisation:
              batched graph-captured steps with fp32 vectors against per-sector
@@ -355,8 +356,9 @@ def row_learned(torch, mbr, reps, big: bool):
                 "unit": "TFLOP/s", "frac": flops / (mlp_ms * 1e-3) / 1e12 / 2500.0,
                 "kernel": "mlp_forward_kernel (12,416 flop per query, bf16 MFMA, fp32 accumulation)"}}
         res["learned_train"] = ("8 epochs x min(N_s, 2^22) samples, batch 4096, Adam lr 2e-3, seed 4; "
-                                "2^b leaves, about 4 members per leaf")
-        rankers = [("trie_k8", trie), ("learned", lr_)]
+                                "2^b leaves, about 4 members per leaf, at most 2^12")
+        # the same search without the network: the whole list is the window
+        rankers = [("trie_k8", trie), ("learned", lr_), ("sampled_search_no_net", mbr.build_sampled_ranker(s))]
         if spin is not None:
             rankers.append(("spin_staggered", mbr.build_spin_ranker(*spin, k=7)))
         ranked = torch.empty(nq, dtype=torch.int32, device="cuda")

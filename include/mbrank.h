@@ -120,6 +120,7 @@ typedef struct mbr_ranker mbr_ranker;
 #define MBR_RANKER_LEARNED   4
 #define MBR_RANKER_BISECT    5
 #define MBR_RANKER_CNS       6
+#define MBR_RANKER_SAMPLED   7
 
 typedef struct {
     int32_t kind;       /* MBR_RANKER_* */
@@ -201,12 +202,13 @@ mbr_status mbr_trie_level_entries(const mbr_ranker *r, uint64_t *entries, int32_
  * index.  Stage 1 is a 32->64->64->1 ReLU network with bf16 weights and fp32
  * accumulation that predicts y ~ rank/size from the 32 bit features; it is
  * trained on the GPU on the sector's own list (Adam, mean squared error).
- * Stage 2 has n_leaves = 2^b leaves (about one per four members); leaf
- * floor(y 2^b) records the smallest and largest rank of the members the
- * network sends to it, measured with the query kernel's own arithmetic.  A
- * query takes the lower bound of its pattern in states[lo..hi] of its leaf
- * (through sampled copies of every 16^l-th state, which the ranker holds on
- * the device, about 1/15 of the list), so ranks are exact.  The recorded
+ * Stage 2 has n_leaves = 2^b leaves (opts->log2_leaves, or about one per
+ * four members up to 2^12); leaf floor(y 2^b) records the smallest and
+ * largest rank of the members the network sends to it, measured with the
+ * query kernel's own arithmetic.  A query takes the lower bound of its
+ * pattern in states[lo..hi] of its leaf (through sampled copies of every
+ * 16^l-th state, which the ranker holds on the device, about 1/15 of the
+ * list), so ranks are exact.  The recorded
  * error e is the widest leaf window hi - lo; when it exceeds opts->max_window,
  * `fallback` answers instead (the fallback must rank the same sector; the
  * learned ranker keeps a reference to it and to `s`).  width_bits must be 32.
@@ -218,10 +220,23 @@ typedef struct {
     uint64_t seed;      /* weight initialisation and sample order */
     uint64_t max_window;/* largest leaf window e still served by the window search */
     uint64_t samples_per_epoch; /* 0 = whole list */
+    int32_t log2_leaves; /* stage-2 leaves 2^b, b in [8, 28]; 0 = about one per four members, at most 2^12 */
 } mbr_learned_opts;
 
 mbr_status mbr_learned_train(const mbr_sector *s, const mbr_learned_opts *opts,
                              const mbr_ranker *fallback, mbr_ranker **out, void *stream);
+
+/* The learned ranker's search without its network (extension, not in the
+ * paper): the lower bound of a pattern in the whole of the sector's ascending
+ * list, by a bisection of the top sampled copy (every 16^H-th state, at most
+ * 8192 entries, staged in LDS) and then one aligned line of 16 entries per
+ * lower copy and one in the list, found when the entry equals the pattern.
+ * It is what a learned ranker's windows are measured against.  width_bits
+ * must be 32 and the sector size below MBR_NOT_FOUND (ERANGE); the ranker
+ * keeps a reference to `s` (destroy it first) and holds the copies, about
+ * 1/15 of the list, on the device.  Answers MBR_NOT_FOUND outside the sector.
+ * Synchronises `stream`. */
+mbr_status mbr_build_sampled_ranker(const mbr_sector *s, mbr_ranker **out, void *stream);
 
 /* Recorded error e of a learned ranker (widest leaf window, hi - lo), and
  * whether it answers through its own window search (1) or the fallback (0). */

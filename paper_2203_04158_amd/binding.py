@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmbrank.so")
 NOT_FOUND = 0xFFFFFFFF
 
-RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED, RANKER_BISECT, RANKER_CNS = 1, 2, 3, 4, 5, 6
+RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED, RANKER_BISECT, RANKER_CNS, RANKER_SAMPLED = (
+    1, 2, 3, 4, 5, 6, 7)
 F64, F32 = 0, 1
 
 _lib = None
@@ -41,7 +42,7 @@ class RankerInfo(C.Structure):
 class LearnedOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
                 ("seed", C.c_uint64), ("max_window", C.c_uint64),
-                ("samples_per_epoch", C.c_uint64)]
+                ("samples_per_epoch", C.c_uint64), ("log2_leaves", C.c_int32)]
 
 
 class LearnedInfo(C.Structure):
@@ -120,6 +121,7 @@ _SIGS = {
                                          C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_rank_batch64": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_build_bisect_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mbr_build_sampled_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
                                          C.c_void_p]),
     "mbr_trie_level_entries": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
@@ -340,6 +342,13 @@ def build_bisect_ranker(sector: Sector) -> Ranker:
     return Ranker(h, keep=(sector,))
 
 
+def build_sampled_ranker(sector: Sector, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_sampled_ranker", lib().mbr_build_sampled_ranker(sector.handle, C.byref(h),
+                                                                      _stream(stream)))
+    return Ranker(h, keep=(sector,))
+
+
 def build_cns_ranker(M: int, N: int, width_bits: int = 32, stream=None) -> Ranker:
     h = C.c_void_p()
     _check("mbr_build_cns_ranker", lib().mbr_build_cns_ranker(M, N, width_bits, C.byref(h),
@@ -358,8 +367,8 @@ def trie_level_entries(ranker: Ranker):
 
 def learned_train(sector: Sector, fallback: Ranker, epochs: int = 4, batch: int = 4096,
                   lr: float = 1e-3, seed: int = 1, max_window: int = 1 << 16,
-                  samples_per_epoch: int = 0, stream=None) -> Ranker:
-    o = LearnedOpts(epochs, batch, lr, seed, max_window, samples_per_epoch)
+                  samples_per_epoch: int = 0, log2_leaves: int = 0, stream=None) -> Ranker:
+    o = LearnedOpts(epochs, batch, lr, seed, max_window, samples_per_epoch, log2_leaves)
     h = C.c_void_p()
     _check("mbr_learned_train", lib().mbr_learned_train(sector.handle, C.byref(o), fallback.handle,
                                                         C.byref(h), _stream(stream)))

@@ -193,3 +193,4 @@ uint64_t trie_bytes(const TrieLevels *t);
 int32_t trie_levels(const TrieLevels *t);
 void learned_free(LearnedModel *m);
 uint64_t learned_bytes(const LearnedModel *m);
+int32_t learned_levels(const LearnedModel *m);  // sampled copies + the list

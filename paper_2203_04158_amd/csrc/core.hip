@@ -122,6 +122,10 @@ mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info) {
             o.bytes = learned_bytes(r->learned);
             o.levels = 0;
             break;
+        case MBR_RANKER_SAMPLED:
+            o.bytes = learned_bytes(r->learned);
+            o.levels = learned_levels(r->learned);
+            break;
         case MBR_RANKER_BISECT:
             o.bytes = r->sector ? r->sector->states.bytes : 0;
             o.levels = 0;
@@ -147,7 +151,8 @@ mbr_status mbr_rank_batch(const mbr_ranker *r, const void *d_q, uint64_t n, uint
         case MBR_RANKER_STAGGERED: return rank_staggered_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_SPIN: return rank_spin_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_TRIE: return rank_trie_launch(r, d_q, n, d_rank, s);
-        case MBR_RANKER_LEARNED: return rank_learned_launch(r, d_q, n, d_rank, s);
+        case MBR_RANKER_LEARNED:
+        case MBR_RANKER_SAMPLED: return rank_learned_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_BISECT: return rank_bisect_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_CNS: return rank_cns_launch(r, d_q, n, d_rank, s);
         default: MBR_FAIL(MBR_EINVAL, "unknown ranker kind %d", r->kind);

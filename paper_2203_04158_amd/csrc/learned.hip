@@ -342,6 +342,10 @@ __device__ __forceinline__ void narrow(PTR smp, uint32_t stride, uint32_t a, uin
     H1 = hi < H1 ? hi : H1;
 }
 
+// NET: the window comes from the network and its leaf; without it the window
+// is the whole list and the search alone ranks (a static 16-ary search over
+// the sampled copies).
+template <bool NET>
 __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__restrict__ wb,
                                                            const uint32_t *__restrict__ states,
                                                            SampleLevels sl,
@@ -352,16 +356,19 @@ __global__ void __launch_bounds__(256) learned_rank_kernel(const uint16_t *__res
     for (uint32_t i = threadIdx.x; i < sl.top_n; i += blockDim.x) top[i] = sl.lv[sl.H - 1][i];
     __syncthreads();
     MlpFrags f;
-    load_frags(f, wb);
+    if constexpr (NET) load_frags(f, wb);
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < nq;
          base += waves * 64) {
         const uint64_t j = base + (threadIdx.x & 63);
         const uint32_t a = j < nq ? q[j] : 0u;
-        const float y = mlp64(f, a);  // every lane of the wave takes part
+        uint2 w = make_uint2(0u, (uint32_t)(sl.n - 1));
+        if constexpr (NET) {
+            const float y = mlp64(f, a);  // every lane of the wave takes part
+            if (j < nq) w = leaf[leaf_of(y, nleaf)];
+        }
         if (j >= nq) continue;
         const bool in_width = M >= 32 || (a >> M) == 0;
-        const uint2 w = leaf[leaf_of(y, nleaf)];
         // lower bound of a in states[lo .. hi] (empty when lo > hi)
         uint32_t L = w.x, R = w.y + 1u;
         bool hit = false;
@@ -622,6 +629,7 @@ mbr_status batch_grad(TrainBufs &T, const float *wr, const uint32_t *q, const fl
 }  // namespace
 
 struct LearnedModel {
+    bool net = true;              // false: sampled-copy search over the whole list
     uint64_t n = 0;
     int32_t M = 0;
     mbr::DevBuf w, m, v, wr, wb;  // masters, Adam moments, rounded fp32, bf16
@@ -637,17 +645,37 @@ struct LearnedModel {
 };
 
 void learned_free(LearnedModel *m) { delete m; }
+int32_t learned_levels(const LearnedModel *m) { return m ? m->n_sample + 1 : 0; }
 uint64_t learned_bytes(const LearnedModel *m) {
     if (!m) return 0;
-    uint64_t b = (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8;
+    uint64_t b = m->net ? (uint64_t)kParams * 2 + (uint64_t)m->n_leaves * 8 : 0;
     for (int l = 0; l < m->n_sample; ++l) b += m->sample[l].bytes;
     return b;
+}
+
+// Sampled copies of the sector list, every kSample^l-th state, until the
+// top one fits kTopMax.
+static mbr_status build_samples(LearnedModel &lm, const mbr_sector *sec, hipStream_t s) {
+    using namespace mbr;
+    uint64_t stride = 1, nb = sec->n;
+    lm.n_sample = 0;
+    do {
+        stride *= kSample;
+        nb = (sec->n + stride - 1) / stride;
+        const uint64_t npad = (nb + kSample - 1) / kSample * kSample;
+        DevBuf &d = lm.sample[lm.n_sample++];
+        MBR_TRY(d.alloc(npad * 4));
+        sample_kernel<<<grid_for(npad, 256, device_cu_count() * 8), 256, 0, s>>>(
+            sec->states.as<uint32_t>(), (uint32_t)stride, d.as<uint32_t>(), nb, npad);
+    } while (nb > kTopMax && lm.n_sample < kMaxLevels);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
 }
 
 mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                                hipStream_t s) {
     const LearnedModel &lm = *r->learned;
-    if (!lm.uses_window) {
+    if (lm.net && !lm.uses_window) {
         if (!r->fallback) MBR_FAIL(MBR_EINVAL, "learned ranker without window or fallback");
         return mbr_rank_batch(r->fallback, q, n, out, s);
     }
@@ -661,9 +689,10 @@ mbr_status rank_learned_launch(const mbr_ranker *r, const void *q, uint64_t n, u
     }
     sl.top_n = (uint32_t)((lm.n + stride - 1) / stride);
     sl.n = lm.n;
-    learned_rank_kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(), sl,
-                                             lm.leaf.as<uint2>(), lm.n_leaves, lm.M,
-                                             static_cast<const uint32_t *>(q), n, out);
+    auto kernel = lm.net ? learned_rank_kernel<true> : learned_rank_kernel<false>;
+    kernel<<<grid, 256, 0, s>>>(lm.wb.as<uint16_t>(), r->sector->states.as<uint32_t>(), sl,
+                                lm.leaf.as<uint2>(), lm.n_leaves, lm.M, static_cast<const uint32_t *>(q), n,
+                                out);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
@@ -701,9 +730,13 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
     if (!sec || !o) MBR_FAIL(MBR_EINVAL, "null sector or options");
     if (sec->width_bits != 32) MBR_FAIL(MBR_EUNSUPPORTED, "learned ranking needs 32-bit patterns");
     if (sec->n < 2) MBR_FAIL(MBR_EINVAL, "sector of %llu states", (unsigned long long)sec->n);
+    if (sec->n >= MBR_NOT_FOUND) MBR_FAIL(MBR_ERANGE, "ranks of %llu states do not fit below MBR_NOT_FOUND",
+                                          (unsigned long long)sec->n);
     if (o->epochs < 0 || o->batch < 256 || o->batch % 256 != 0 || o->batch > (1 << 20))
         MBR_FAIL(MBR_EINVAL, "epochs=%d batch=%d (batch: multiple of 256 up to 2^20)", o->epochs, o->batch);
     if (!(o->lr > 0.f)) MBR_FAIL(MBR_EINVAL, "lr must be positive");
+    if (o->log2_leaves != 0 && (o->log2_leaves < 8 || o->log2_leaves > 28))
+        MBR_FAIL(MBR_EINVAL, "log2_leaves=%d (0, or 8 to 28)", o->log2_leaves);
     if (fallback && fallback->n_states != sec->n) MBR_FAIL(MBR_EINVAL, "fallback ranks a different sector");
     hipStream_t s = as_stream(stream);
     auto lm = std::make_unique<LearnedModel>();
@@ -746,25 +779,17 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
                                            d_e.as<unsigned long long>());
     MBR_HIP(hipGetLastError());
     // stage 2: leaf windows (about four members per leaf), then their statistics
+    // Automatic: about four members per leaf, at most 2^12 leaves.  The table
+    // (32 KB) then stays in every L2; with many more leaves the leaf read
+    // becomes a gather from HBM that costs more than the narrower windows
+    // save (2^26 leaves: 13.0 against 16.3 Granks/s on a 165.6 M sector).
     uint64_t nl = 256;
-    while (nl < sec->n / 4 && nl < (1ull << 26)) nl <<= 1;
+    if (o->log2_leaves) nl = 1ull << o->log2_leaves;
+    else
+        while (nl < sec->n / 4 && nl < (1ull << 12)) nl <<= 1;
     lm->n_leaves = (uint32_t)nl;
     MBR_TRY(lm->leaf.alloc(nl * 8));
-    // sampled copies, every kSample^l-th state, until the top one fits kTopMax
-    {
-        uint64_t stride = 1, nb = sec->n;
-        lm->n_sample = 0;
-        do {
-            stride *= kSample;
-            nb = (sec->n + stride - 1) / stride;
-            const uint64_t npad = (nb + kSample - 1) / kSample * kSample;
-            DevBuf &d = lm->sample[lm->n_sample++];
-            MBR_TRY(d.alloc(npad * 4));
-            sample_kernel<<<grid_for(npad, 256, device_cu_count() * 8), 256, 0, s>>>(
-                sec->states.as<uint32_t>(), (uint32_t)stride, d.as<uint32_t>(), nb, npad);
-        } while (nb > kTopMax && lm->n_sample < kMaxLevels);
-        MBR_HIP(hipGetLastError());
-    }
+    MBR_TRY(build_samples(*lm, sec, s));
     leaf_clear_kernel<<<(unsigned)((nl + 255) / 256), 256, 0, s>>>(lm->leaf.as<uint2>(), (uint32_t)nl);
     leaf_build_kernel<<<grid, 256, 0, s>>>(lm->wb.as<uint16_t>(), sec->states.as<uint32_t>(), sec->n,
                                            (uint32_t)nl, lm->leaf.as<uint2>());
@@ -797,6 +822,36 @@ mbr_status mbr_learned_train(const mbr_sector *sec, const mbr_learned_opts *o,
     (void)hipGetDevice(&r->device);
     r->learned = lm.release();
     *out = r;
+    return MBR_OK;
+}
+
+mbr_status mbr_build_sampled_ranker(const mbr_sector *sec, mbr_ranker **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!sec) MBR_FAIL(MBR_EINVAL, "null sector");
+    if (sec->width_bits != 32) MBR_FAIL(MBR_EUNSUPPORTED, "the sampled search needs 32-bit patterns");
+    if (sec->n == 0) MBR_FAIL(MBR_EINVAL, "empty sector");
+    if (sec->n >= MBR_NOT_FOUND) MBR_FAIL(MBR_ERANGE, "ranks of %llu states do not fit below MBR_NOT_FOUND",
+                                          (unsigned long long)sec->n);
+    hipStream_t s = as_stream(stream);
+    auto lm = std::make_unique<LearnedModel>();
+    lm->net = false;
+    lm->n = sec->n;
+    lm->M = sec->M;
+    lm->uses_window = 1;
+    MBR_TRY(build_samples(*lm, sec, s));
+    MBR_HIP(hipStreamSynchronize(s));
+    auto r = std::make_unique<mbr_ranker>();
+    r->kind = MBR_RANKER_SAMPLED;
+    r->M = sec->M;
+    r->k = 0;
+    r->width_bits = 32;
+    r->n_states = sec->n;
+    r->sector = sec;
+    (void)hipGetDevice(&r->device);
+    r->learned = lm.release();
+    *out = r.release();
     return MBR_OK;
 }
 

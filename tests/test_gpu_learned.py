@@ -122,7 +122,8 @@ def test_learned_ranks_exact_and_error_recorded():
     y = mbr.mlp_forward(params, dev_u32(np.concatenate([st, np.zeros((-st.size) % 64, np.uint64)])))
     y = y.cpu().numpy()[: st.size]
     nl = info["n_leaves"]
-    assert nl >= st.size // 4 and nl & (nl - 1) == 0
+    # automatic: about four members per leaf, between 2^8 and 2^12 leaves
+    assert nl == min(1 << 12, max(256, 1 << (st.size // 4 - 1).bit_length()))
     b, lo, hi = _leaf_windows(y, nl, st.size)
     assert int((hi - lo)[hi >= 0].max()) == e
     assert abs(info["mean_window"] - float((hi[b] - lo[b] + 1).mean())) <= 1e-9 * info["mean_window"]
@@ -210,3 +211,56 @@ def test_learned_ranks_exact_on_small_and_ragged_sectors(M, N):
     noise = synth.splitmix64(M * 7 + N, 20000) & np.uint64((1 << (M + 1)) - 1)
     got = host_rank(mbr.rank_batch(lr_, dev_u32(noise)))
     assert np.array_equal(got, OC.bisect_rank(st, noise))
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (17, 1), (10, 4), (11, 4), (12, 5), (16, 3), (20, 10)])
+def test_sampled_search_ranks_exact(M, N):
+    """The search without the network (whole list as the window): sector sizes
+    1, 17, 210, 330, 792, 560 and 184,756 cover one to four sampled copies,
+    ragged last lines and the bisection tail; every member and seeded
+    non-members (bits above M included) against the oracle's bisection."""
+    cons = OC.constraints(M, N)
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons)
+    r = mbr.build_sampled_ranker(s)
+    info = r.info()
+    assert info.kind == mbr.RANKER_SAMPLED and info.n_states == st.size
+    got = host_rank(mbr.rank_batch(r, dev_u32(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    noise = synth.splitmix64(M * 11 + N, 30001) & np.uint64((1 << min(M + 1, 32)) - 1)
+    got = host_rank(mbr.rank_batch(r, dev_u32(noise)))
+    assert np.array_equal(got, OC.bisect_rank(st, noise))
+
+
+def test_sampled_search_chain_sector_and_rejects():
+    """Full-size (7,7) chain sector (11,778,624 states, three sampled copies):
+    every member, and 2^20 seeded 28-bit patterns against the oracle; 64-bit
+    sectors are refused."""
+    M, cons = 28, OC.spin_constraints(14, 7, 7)
+    s = mbr.sector_build(M, cons)
+    r = mbr.build_sampled_ranker(s)
+    idx = torch.arange(s.size, dtype=torch.int32, device="cuda")
+    assert torch.equal(mbr.rank_batch(r, s.states()), idx)
+    st = OC.sector_enumerate(M, cons)
+    noise = synth.splitmix64(91, 1 << 20) & np.uint64((1 << 28) - 1)
+    assert np.array_equal(host_rank(mbr.rank_batch(r, dev_u32(noise))), OC.bisect_rank(st, noise))
+    s64 = mbr.sector_build(40, OC.constraints(40, 1), width_bits=64)
+    with pytest.raises(mbr.MbrError):
+        mbr.build_sampled_ranker(s64)
+
+
+def test_leaf_count_option():
+    """An explicit 2^b leaves is honoured (ranks stay exact); b outside 8..28
+    is refused."""
+    M, cons = 12, OC.constraints(12, 5)
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons)
+    trie = mbr.build_trie(s, 4)
+    for b in (8, 11):
+        r = mbr.learned_train(s, trie, epochs=2, batch=256, lr=3e-3, seed=2, max_window=1 << 20,
+                              log2_leaves=b)
+        assert mbr.learned_stats(r)["n_leaves"] == 1 << b
+        assert np.array_equal(host_rank(mbr.rank_batch(r, dev_u32(st))), np.arange(st.size))
+    for b in (7, 29, -1):
+        with pytest.raises(mbr.MbrError):
+            mbr.learned_train(s, trie, epochs=1, batch=256, log2_leaves=b)
