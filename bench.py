@@ -311,6 +311,12 @@ def row_trie(torch, mbr, reps):
                         "level_bytes": [4 * e for e in ent], "trie_bytes": int(info.bytes),
                         "overhead_f": info.bytes / 4 / s.size, "roofline": roof}
         del r
+    # the learned ranker's search without its network, on the same queries
+    r = mbr.build_sampled_ranker(s)
+    ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
+    res["sampled_search_no_net"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
+                                    "exact": bool(torch.equal(out, want)), "table_bytes": int(r.info().bytes),
+                                    "levels": r.info().levels}
     return res
 
 
