@@ -72,14 +72,24 @@ __global__ void __launch_bounds__(kBlock) trie_rank_kernel(const P *__restrict__
             if (!ok[u]) x[u] = 0;
             node[u] = 0;
         }
-        // the walks of kQ queries advance level by level side by side
-        for (int l = 0; l < a.H; ++l) {
-            const uint32_t *lv = (l < a.lds_levels) ? nullptr : a.tab + a.off[l];
+        // the walks of kQ queries advance level by level side by side; the
+        // staged levels and the rest are separate loops, so that LDS is read
+        // with LDS loads and the arrays with global loads (one loop choosing
+        // per level compiles to flat loads for both)
+        int l = 0;
+        for (; l < a.lds_levels; ++l) {
 #pragma unroll
             for (int u = 0; u < kQ; ++u) {
                 const uint32_t c = (uint32_t)(x[u] >> a.shift[l]) & a.wmask[l];
-                const uint32_t idx = node[u] + c;
-                node[u] = lv ? lv[idx] : top[a.off[l] + idx];
+                node[u] = top[a.off[l] + node[u] + c];
+            }
+        }
+        for (; l < a.H; ++l) {
+            const uint32_t *lv = a.tab + a.off[l];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) {
+                const uint32_t c = (uint32_t)(x[u] >> a.shift[l]) & a.wmask[l];
+                node[u] = lv[node[u] + c];
             }
         }
         P hit[kQ];
