@@ -94,6 +94,21 @@ mbr_status mbr_sector_build_mod(int32_t M, int32_t width_bits, int32_t n_cons, c
                                 const int32_t *weights, int32_t modulus, int32_t residue,
                                 mbr_sector **out, void *stream);
 
+/* Adopt a sector the caller has listed (Sec. IV, last paragraph: sets that
+ * only a filter describes, such as the total-momentum blocks, are fed to the
+ * trie builder in ascending order).  d_states holds n patterns (device memory,
+ * uint32 or uint64 per width_bits, M in 1..64, M <= 32 for 32-bit patterns);
+ * they are copied into a new library-owned sector, so the caller may free
+ * them on return.  The copy is checked on the device, and the first offending
+ * position j decides the status: MBR_ENOTSORTED when entry j is smaller than
+ * entry j-1, MBR_EDUP when it equals entry j-1, MBR_EINVAL when entry j has
+ * bits at or above M (order is checked before width at one position).
+ * MBR_ERANGE for n >= 2^32 - 1.  n = 0 gives an empty sector.  No popcount
+ * window describes such a sector, so operators on it always check membership.
+ * Synchronises `stream`.  *out receives the handle. */
+mbr_status mbr_sector_from_list(int32_t M, int32_t width_bits, const void *d_states, uint64_t n,
+                                mbr_sector **out, void *stream);
+
 /* Number of states in the sector. */
 mbr_status mbr_sector_size(const mbr_sector *s, uint64_t *n);
 
@@ -184,9 +199,9 @@ mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void
 /* The established methods the paper compares against (Sec. III, Sec. V.A).
  * Bisection: lower bound of the pattern in the sector's ascending list, found
  * when the entry equals the pattern; any sector; the ranker keeps a reference
- * to `s` (destroy it first).  Combinadics: Eq. cns by the bit walk of Fig.
- * algr (for the k-th set bit from the least significant end, at position c,
- * add C(c, k)) for the particle-number sector of N out of M orbitals; ranks
+ * to `s` (destroy it first).  Combinadics: Eq. cns, the sum of C(c_k, k)
+ * over the occupied positions c_1 < ... < c_N (Sec. III.A), taken position by
+ * position, for the particle-number sector of N out of M orbitals; ranks
  * must fit 32 bits (ERANGE).  Both answer MBR_NOT_FOUND outside the sector. */
 mbr_status mbr_build_bisect_ranker(const mbr_sector *s, mbr_ranker **out);
 mbr_status mbr_build_cns_ranker(int32_t M, int32_t N, int32_t width_bits, mbr_ranker **out,
@@ -363,7 +378,7 @@ typedef struct {
 
 typedef struct {
     int32_t L;                       /* sites, 1..16 */
-    int32_t n_bonds;                 /* 0..64 */
+    int32_t n_bonds;                 /* 0..48 */
     const mbr_bond *bonds;
     const double *eps;               /* on-site energies [L] or NULL */
     const double *U;                 /* on-site interaction [L] or NULL */
@@ -389,10 +404,15 @@ mbr_status mbr_hubbard_apply(const mbr_hubbard *h, const void *d_x, void *d_y, v
 mbr_status mbr_hubbard_destroy(mbr_hubbard *h);
 
 /* Launch shape of the H·x kernel (extension: the paper has no GPU layout).
- * k: half-pattern chunk width of the staggered rank; G: alpha_up blocks a
- * workgroup holds (the down-hop ranks of a lane are reused G times); block:
- * threads per workgroup (256 or 512).  tuned_ms is the autotuner's best time
- * for one product (0 when not tuned). */
+ * k: half-pattern chunk width of the staggered rank; G: 0 selects the
+ * alpha_dn-stationary rows kernel (1024-lane workgroups, one per CU, down-hop
+ * lists ranked once per launch shape) for every sector it supports (at most
+ * 4095 spin-down configurations and 15 bonds) and the tile kernel with two
+ * blocks for the rest; G in {1,2,4} selects the tile kernel for every sector,
+ * holding G alpha_up blocks per workgroup (the down-hop ranks of a lane are
+ * reused G times); block: threads per workgroup of the tile kernel (256 or
+ * 512).  tuned_ms is the autotuner's best time for one product (0 when not
+ * tuned). */
 typedef struct {
     int32_t k;
     int32_t G;
@@ -404,7 +424,7 @@ typedef struct {
 
 mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg);
 
-/* Set the launch shape (k in 1..L, G in {1,2,4}, block in {256,512}); EUNSUPPORTED
+/* Set the launch shape (k in 1..L, G in {0,1,2,4}, block in {256,512}); EUNSUPPORTED
  * when the tiles would not fit the LDS.  Lanczos handles created before the
  * change reject further steps (EINVAL): create them afterwards. */
 mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream);

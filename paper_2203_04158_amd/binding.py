@@ -91,6 +91,8 @@ _SIGS = {
     "mbr_version": (C.c_int32, []),
     "mbr_sector_build": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(PopcCons),
                                      C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_sector_from_list": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_uint64,
+                                         C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_sector_size": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "mbr_sector_states": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mbr_sector_destroy": (C.c_int32, [C.c_void_p]),
@@ -243,6 +245,17 @@ def sector_build(M: int, constraints, width_bits: int = 32, stream=None) -> Sect
     h = C.c_void_p()
     _check("mbr_sector_build", lib().mbr_sector_build(M, width_bits, len(cons), arr, C.byref(h),
                                                       _stream(stream)))
+    return Sector(h, M, width_bits)
+
+
+def sector_from_list(M: int, states, width_bits: int = 32, stream=None) -> Sector:
+    """A sector holding the caller's ascending device list `states` (int32 or
+    int64 storage of uint32/uint64 patterns), copied and checked by the library."""
+    n = states.numel()
+    h = C.c_void_p()
+    ptr = _dvec(states, width_bits // 8, n, "states") if n else None
+    _check("mbr_sector_from_list", lib().mbr_sector_from_list(M, width_bits, ptr, n, C.byref(h),
+                                                              _stream(stream)))
     return Sector(h, M, width_bits)
 
 

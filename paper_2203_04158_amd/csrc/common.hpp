@@ -117,6 +117,7 @@ struct mbr_sector {
     std::vector<mbr_popc_cons> cons;
     int32_t modulus = 0, residue = 0;  // modular weight constraint (modulus 0: none)
     std::vector<int32_t> weights;      // orbital weights mod modulus (modulus > 0)
+    bool from_list = false;            // adopted from a caller's list: no constraint describes it
     mbr::DevBuf states;
 };
 

@@ -8,6 +8,7 @@
 // pattern of equal popcount with Gosper's rule.  Runs are visited in increasing
 // order, so a count pass, an exclusive scan of the per-run counts and a write
 // pass give the sorted list without any sort.
+#include <memory>
 #include <numeric>
 
 #include "common.hpp"
@@ -105,6 +106,32 @@ __global__ void sector_fill_kernel(uint64_t S, uint64_t run, int N, int M, ConsS
         if (in_sector(a, cs)) out[o++] = static_cast<P>(a);
         if (j + 1 < len) a = run_next<FIXED>(a);
     }
+}
+
+// First position that breaks a caller's list: for j >= 1, list[j] below its
+// predecessor (code 1), equal to it (code 2), or any entry with bits at or
+// above M (code 3).  The smallest (position << 2 | code) wins, so the first
+// offending position decides and the result does not depend on scheduling.
+template <class P>
+__global__ void list_check_kernel(const P *__restrict__ a, uint64_t n, int M, unsigned long long *first) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long best = ~0ull;
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
+        const P v = a[j];
+        unsigned code = 0;
+        if (M < (int)(8 * sizeof(P)) && (v >> M) != 0) code = 3;
+        if (j > 0) {
+            const P u = a[j - 1];
+            if (u > v) code = 1;
+            else if (u == v) code = 2;
+        }
+        if (code) {
+            const unsigned long long key = ((unsigned long long)j << 2) | code;
+            best = key < best ? key : best;
+            break;  // later positions of this lane cannot be smaller
+        }
+    }
+    if (best != ~0ull) atomicMin(first, best);
 }
 
 template <class P>
@@ -252,6 +279,54 @@ mbr_status mbr_sector_build_mod(int32_t M, int32_t width_bits, int32_t n_cons, c
                                 mbr_sector **out, void *stream) {
     if (modulus < 1) MBR_FAIL(MBR_EINVAL, "modulus %d must be positive", modulus);
     return sector_build_impl(M, width_bits, n_cons, cons, weights, modulus, residue, out, stream);
+}
+
+mbr_status mbr_sector_from_list(int32_t M, int32_t width_bits, const void *d_states, uint64_t n,
+                                mbr_sector **out, void *stream) {
+    using namespace mbr;
+    if (!out) MBR_FAIL(MBR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (M < 1 || M > 64) MBR_FAIL(MBR_EINVAL, "M=%d outside 1..64", M);
+    if (width_bits != 32 && width_bits != 64) MBR_FAIL(MBR_EINVAL, "width_bits=%d", width_bits);
+    if (width_bits == 32 && M > 32) MBR_FAIL(MBR_EINVAL, "M=%d needs 64-bit patterns", M);
+    if (n > 0 && !d_states) MBR_FAIL(MBR_EINVAL, "null state list");
+    if (n >= 0xFFFFFFFFull) MBR_FAIL(MBR_ERANGE, "list of %llu states", (unsigned long long)n);
+    hipStream_t s = as_stream(stream);
+    auto sec = std::make_unique<mbr_sector>();
+    sec->M = M;
+    sec->width_bits = width_bits;
+    sec->n = n;
+    sec->from_list = true;
+    MBR_HIP(hipGetDevice(&sec->device));
+    const size_t bytes = (size_t)n * (width_bits / 8);
+    MBR_TRY(sec->states.alloc(bytes));
+    if (n > 0) {
+        MBR_HIP(hipMemcpyAsync(sec->states.p, d_states, bytes, hipMemcpyDeviceToDevice, s));
+        const unsigned long long none = ~0ull;
+        DevBuf flag;
+        MBR_TRY(upload(flag, &none, sizeof none, s));
+        const unsigned grid = grid_for(n, 256, device_cu_count() * 8);
+        if (width_bits == 32)
+            list_check_kernel<uint32_t><<<grid, 256, 0, s>>>(sec->states.as<uint32_t>(), n, M,
+                                                             flag.as<unsigned long long>());
+        else
+            list_check_kernel<uint64_t><<<grid, 256, 0, s>>>(sec->states.as<uint64_t>(), n, M,
+                                                             flag.as<unsigned long long>());
+        MBR_HIP(hipGetLastError());
+        unsigned long long first = 0;
+        MBR_HIP(hipMemcpyAsync(&first, flag.p, sizeof first, hipMemcpyDeviceToHost, s));
+        MBR_HIP(hipStreamSynchronize(s));
+        if (first != ~0ull) {
+            const unsigned long long pos = first >> 2;
+            switch (first & 3) {
+                case 1: MBR_FAIL(MBR_ENOTSORTED, "entry %llu is smaller than entry %llu", pos, pos - 1);
+                case 2: MBR_FAIL(MBR_EDUP, "entry %llu repeats entry %llu", pos, pos - 1);
+                default: MBR_FAIL(MBR_EINVAL, "entry %llu has bits at or above M=%d", pos, M);
+            }
+        }
+    }
+    *out = sec.release();
+    return MBR_OK;
 }
 
 mbr_status mbr_sector_size(const mbr_sector *s, uint64_t *n) {

@@ -409,7 +409,8 @@ mbr_status mbr_operator_create(const mbr_sector *sec, const mbr_ranker *rk, cons
     std::vector<uint32_t> keep(n, 0u);
     for (int64_t i = 0; i < n_terms; ++i) {
         const uint64_t lo = terms[i].l, hi = terms[i].l ^ terms[i].x;
-        bool k = true;
+        // a caller's list has no constraints to check a tuple against
+        bool k = !sec->from_list;
         for (const mbr_popc_cons &c : sec->cons)
             k = k && __builtin_popcountll(lo & c.mask) == __builtin_popcountll(hi & c.mask);
         if (sec->modulus > 0) {

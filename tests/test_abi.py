@@ -36,3 +36,17 @@ def test_argument_validation_without_gpu():
     assert L.mbr_sector_build(65, 64, 0, None, ctypes.byref(h), None) == -1
     assert L.mbr_rank_batch(None, None, 1, None, None) == -1
     assert b"null" in L.mbr_last_error()
+
+
+def test_sector_from_list_argument_errors_without_gpu():
+    # every one of these is refused before the list is touched
+    L = mbr.lib()
+    h = ctypes.c_void_p()
+    assert L.mbr_sector_from_list(0, 32, None, 0, ctypes.byref(h), None) == -1      # M
+    assert L.mbr_sector_from_list(40, 32, None, 0, ctypes.byref(h), None) == -1     # M > 32 in 32 bits
+    assert L.mbr_sector_from_list(12, 16, None, 0, ctypes.byref(h), None) == -1     # width
+    assert L.mbr_sector_from_list(12, 32, None, 5, ctypes.byref(h), None) == -1     # null list
+    assert b"null state list" in L.mbr_last_error()
+    assert L.mbr_sector_from_list(12, 32, ctypes.c_void_p(16), 0xFFFFFFFF, ctypes.byref(h), None) == -6
+    assert L.mbr_sector_from_list(12, 32, None, 0, None, None) == -1                # null handle
+    assert L.mbr_status_str(-5) == b"state list has duplicates"

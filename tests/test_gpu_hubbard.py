@@ -32,6 +32,21 @@ def _dev(a, prec):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
 
 
+def _oracle_apply_all(st, tl, x):
+    """The oracle's product over every row of a sector, its row ranges run on
+    host threads side by side (the C oracle releases the interpreter lock)."""
+    import concurrent.futures as cf
+    n = st.size
+    if n < 200000:
+        return OH.apply(st, tl, x, with_abssum=True)
+    nt = min(16, os.cpu_count() or 1)
+    cuts = np.linspace(0, n, 4 * nt + 1).astype(np.int64)
+    with cf.ThreadPoolExecutor(nt) as ex:
+        parts = list(ex.map(lambda ab: OH.apply(st, tl, x, with_abssum=True, row_range=ab),
+                            zip(cuts[:-1], cuts[1:])))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
 def _check_apply(L, bonds, sectors, U, eps, prec, seed, k=0, rows_per_sector=None):
     h = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps, precision=prec, k=k)
     x = 2 * synth.uniform01(seed, h.dim) - 1
@@ -48,7 +63,7 @@ def _check_apply(L, bonds, sectors, U, eps, prec, seed, k=0, rows_per_sector=Non
         st = OH.sector(L, nu, nd)
         assert st.size == o1 - o0
         if rows_per_sector is None:
-            want, ab = OH.apply(st, tl, x[o0:o1], with_abssum=True)
+            want, ab = _oracle_apply_all(st, tl, x[o0:o1])
             got = y[o0:o1]
         else:
             n = st.size
@@ -95,19 +110,23 @@ def test_narrow_tiles_many_sectors_fp32():
     _check_apply(L, OH.star_bonds(V), sectors, U, eps, mbr.F32, seed=3, rows_per_sector=3000)
 
 
-def test_chain_l14_full_size_sampled():
+@pytest.mark.timeout(600)
+def test_chain_l14_all_rows():
+    # every one of the 11,778,624 rows of the headline product, in the default
+    # launch shape (other shapes give bitwise equal products, tested below)
     L = 14
-    _check_apply(L, OH.chain_bonds(L), [(7, 7)], [4.0] * L, None, mbr.F64, seed=2,
-                 rows_per_sector=4000)
+    h = _check_apply(L, OH.chain_bonds(L), [(7, 7)], [4.0] * L, None, mbr.F64, seed=2)
+    say("L=14 launch shape", mbr.hubbard_get_config(h))
 
 
-def test_anderson_all_169_sectors_sampled_fp32():
+@pytest.mark.timeout(600)
+def test_anderson_all_169_sectors_all_rows_fp32():
     L = 12
     eps_b, V = synth.anderson_parameters(5, 11)
     eps = [-4.0] + list(eps_b)
     U = [8.0] + [0.0] * 11
     sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
-    h = _check_apply(L, OH.star_bonds(V), sectors, U, eps, mbr.F32, seed=5, rows_per_sector=60)
+    h = _check_apply(L, OH.star_bonds(V), sectors, U, eps, mbr.F32, seed=5)
     assert h.dim == 1 << 24
 
 

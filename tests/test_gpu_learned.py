@@ -264,3 +264,50 @@ def test_leaf_count_option():
     for b in (7, 29, -1):
         with pytest.raises(mbr.MbrError):
             mbr.learned_train(s, trie, epochs=1, batch=256, log2_leaves=b)
+
+
+def _m32_8x8_list():
+    """The sector M = 32 with 8 particles in each 16-bit half (165,636,900
+    states), ascending.  Its members are the pairs (upper half, lower half) of
+    two 8-of-16 patterns, and ascending order is the order of the upper half,
+    then of the lower; the list is built that way from the oracle's 16-bit
+    sector and checked against the oracle's enumeration at M = 20."""
+    def pairs(h):
+        half = OC.sector_enumerate(h, OC.constraints(h, h // 2))
+        return ((half[:, None] << np.uint64(h)) | half[None, :]).ravel()
+    small = pairs(10)
+    assert np.array_equal(small, OC.sector_enumerate(20, OC.spin_constraints(10, 5, 5)))
+    st = pairs(16)
+    assert st.size == 12870 ** 2
+    return st
+
+
+@pytest.mark.timeout(900)
+def test_learned_and_sampled_m32_8x8_full_size():
+    """Ranking config 4(b): M = 32, N_up = N_dn = 8 (165,636,900 states; four
+    sampled copies and bit 31 in use), trained as in the benchmark with the
+    window search forced.  Every member ranks to its index, and 2^20 uniform
+    members plus 2^20 arbitrary 32-bit patterns agree with bisection on the
+    oracle's list, for the learned ranker and for the same search without the
+    network."""
+    M, cons = 32, OC.spin_constraints(16, 8, 8)
+    st = _m32_8x8_list()
+    s = mbr.sector_build(M, cons)
+    assert s.size == st.size
+    states = s.states()
+    assert np.array_equal(states.cpu().numpy().view(np.uint32), st.astype(np.uint32))
+    sampled = mbr.build_sampled_ranker(s)
+    lr_ = mbr.learned_train(s, sampled, epochs=8, batch=4096, lr=2e-3, seed=4,
+                            samples_per_epoch=1 << 22, max_window=1 << 31)
+    info = mbr.learned_stats(lr_)
+    say("m32 8+8 learned", info, "sampled levels", sampled.info().levels)
+    assert info["uses_window"]
+    idx = torch.arange(s.size, dtype=torch.int32, device="cuda")
+    noise = synth.splitmix64(80, 1 << 20) & np.uint64(0xFFFFFFFF)
+    noise[:4] = [0, 0xFFFFFFFF, 1 << 31, 0xFF00FF00]
+    q = np.concatenate([st[synth.uniform_indices(81, 1 << 20, st.size)], noise])
+    want = OC.bisect_rank(st, q)
+    for name, r in (("learned", lr_), ("sampled", sampled)):
+        say("m32 8+8 all members:", name)
+        assert torch.equal(mbr.rank_batch(r, states), idx), name
+        assert np.array_equal(host_rank(mbr.rank_batch(r, dev_u32(q))), want), name

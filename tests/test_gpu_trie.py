@@ -98,6 +98,17 @@ def test_ras_m32_full_size(k):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("N", [14, 5])
+def test_m28_k12(N):
+    """R = 12 at M = 28, the largest chunk width of the paper's sweep (Sec.
+    V.A): chunks of 12, 12 and 4 bits; half filling (40,116,600 states) and
+    N = 5 (98,280), where the trie is mostly padding.  Every member, seeded
+    arbitrary 28-bit and 29-bit patterns, sizes against the packed count."""
+    r = _check(28, OC.constraints(28, N), 12, n_noise=1 << 20, seed=N)
+    say("M=28 N", N, "k=12 bytes", r.info().bytes)
+
+
 def test_trie_rejects_bad_args():
     s = mbr.sector_build(10, OC.constraints(10, 5))
     with pytest.raises(mbr.MbrError):
