@@ -19,7 +19,7 @@ _lib = None
 def build() -> str:
     """Compile oracle.c into liboracle.so (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-fopenmp", "-shared", "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -46,6 +46,10 @@ def lib() -> ctypes.CDLL:
     L.orc_apply_terms_bra.argtypes = [p, i64, i32, p, p, p, p, p, p, p, p, i64, i64]
     L.orc_terms_coo.restype = i64
     L.orc_terms_coo.argtypes = [p, i64, i32, p, p, p, p, p, p, p, p, i64]
+    L.orc_hubbard_bisect_apply.restype = i64
+    L.orc_hubbard_bisect_apply.argtypes = [p, i64, i32, i32, p, p, p, p, p, p, p, i64, i64, i32]
+    L.orc_rank_batch_mt.restype = None
+    L.orc_rank_batch_mt.argtypes = [p, i64, p, i64, p, i32, i32]
     _lib = L
     return L
 

@@ -18,7 +18,7 @@ def binom(n: int, k: int) -> int:
 
 
 def cns_rank(alpha: int) -> int:
-    """Eq. cns / Eq. rank via the ctz loop of the combinadics ranking figure."""
+    """Eq. cns / Eq. rank: sum of C(c_k, k) over the occupied positions c_1 < ... < c_N."""
     return int(lib().orc_cns_rank(alpha))
 
 
@@ -91,3 +91,14 @@ def bisect_rank(states, q) -> np.ndarray:
 def unrank(states, idx) -> np.ndarray:
     """Unrank by the stored list (Sec. II): unrank(i) = states[i]."""
     return np.asarray(states)[np.asarray(idx)]
+
+
+def rank_batch_threads(states, q, method: str, threads: int) -> np.ndarray:
+    """bisect_rank ('bisect') or cns_rank_batch ('cns') over `threads` OpenMP
+    threads (timing leg only; same results as the single-thread functions)."""
+    states = np.ascontiguousarray(states, dtype=np.uint64)
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    out = np.empty(q.size, dtype=np.int64)
+    lib().orc_rank_batch_mt(ptr(states), states.size, ptr(q), q.size, ptr(out),
+                            0 if method == "bisect" else 1, threads)
+    return out

@@ -56,6 +56,27 @@ def terms(L: int, bonds, U, eps=None):
     return [t for t in out if t[0] != 0]
 
 
+def apply_bisect(states, L: int, bonds, U, eps, x, row_range=None, threads: int = 1):
+    """y = H x over rows row_range (default all) by the plain gather form with
+    bisection ranks (the baseline method of Sec. V.B), on `threads` OpenMP
+    threads.  Same Hamiltonian and conventions as terms()."""
+    states = np.ascontiguousarray(states, dtype=np.uint64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    Ul = np.full(L, float(U)) if np.isscalar(U) else np.asarray(U, dtype=np.float64)
+    el = np.zeros(L) if eps is None else np.asarray(eps, dtype=np.float64)
+    bi = np.array([b[0] for b in bonds] or [0], dtype=np.int32)
+    bj = np.array([b[1] for b in bonds] or [0], dtype=np.int32)
+    bt = np.array([b[2] for b in bonds] or [0.0], dtype=np.float64)
+    r0, r1 = row_range if row_range is not None else (0, states.size)
+    y = np.empty(r1 - r0)
+    rc = lib().orc_hubbard_bisect_apply(ptr(states), states.size, L, len(bonds), ptr(bi), ptr(bj), ptr(bt),
+                                        ptr(np.ascontiguousarray(el)), ptr(np.ascontiguousarray(Ul)),
+                                        ptr(x), ptr(y), r0, r1, threads)
+    if rc != 0:
+        raise ValueError(f"hop target of row {-rc - 1} is outside the sector")
+    return y
+
+
 def _arrays(tl):
     v = np.array([t[0] for t in tl], dtype=np.float64)
     f = [np.array([t[k] for t in tl], dtype=np.uint64) for k in (1, 2, 3, 4, 5)]

@@ -28,25 +28,51 @@ def scale(t, c):
     return (v * c, m, l, r, x, s)
 
 
+def _inside(m: int):
+    """Every pattern whose set bits lie inside the mask m (0 and m included)."""
+    sub = m
+    while True:
+        yield sub
+        if sub == 0:
+            return
+        sub = (sub - 1) & m
+
+
 def mul(ta, tb):
-    """Product rule figure of Appendix A: tuple of T_a T_b from those of T_a, T_b."""
-    va, ma, la, ra, xa, sa = ta
-    vb, mb, lb, rb, xb, sb = tb
-    # Pauli check on the intermediate state where both masks overlap.
-    v = 0 if ((ra ^ lb) & ma & mb) else va * vb
-    m = ma | mb
-    r = rb | (ra & ~mb)
-    l = la | (lb & ~ma)
-    x = l ^ r
-    s = (sa ^ sb) & ~m
-    # Sign of T_a T_b on the state |r>, absorbed into v.
-    z = r
-    p = z & sb
-    z ^= xb
-    p ^= z & sa
-    if _h(p) & 1:
-        v = -v
-    return (v, m, l, r, x, s)
+    """Tuple of the product T_a T_b (T_b acts first), Appendix A, read off from
+    what the product does to states (Eq. Talpha1 applied twice).
+
+    The product touches only the orbitals of m = m_a | m_b.  It is applied to
+    every pattern inside m; for a product of non-branching terms at most one of
+    them survives, and that one is r, with l = its image and x = l ^ r.  v is
+    the coefficient on r itself (no orbital outside m occupied).  An orbital k
+    outside m belongs to the sign mask s when occupying it flips the sign of
+    the product.  No surviving pattern: the product vanishes (v = 0)."""
+    m = ta[1] | tb[1]
+
+    def act(alpha):
+        c1, b1 = apply_ket(tb, alpha)
+        if b1 is None:
+            return 0, None
+        c2, b2 = apply_ket(ta, b1)
+        return (0, None) if b2 is None else (c1 * c2, b2)
+
+    hits = [(beta,) + act(beta) for beta in _inside(m)]
+    hits = [h for h in hits if h[2] is not None]
+    if not hits:
+        return (0, m, 0, 0, 0, 0)
+    assert len(hits) == 1, "a product of non-branching terms is non-branching"
+    r, v, img = hits[0]
+    assert img & ~m == 0
+    s = 0
+    for k in range((m | ta[5] | tb[5]).bit_length()):
+        if (m >> k) & 1:
+            continue
+        c, b = act(r | (1 << k))
+        assert b == img | (1 << k) and abs(c) == abs(v)
+        if c != v:
+            s |= 1 << k
+    return (v, m, img, r, img ^ r, s)
 
 
 def product(*terms):

@@ -44,21 +44,22 @@ uint64_t orc_binom(int n, int k)
 }
 
 /* ---------------------------------------------------------------------------
- * Combinadics rank, Eq. cns with Eq. rank: walk the set bits from the lowest,
- * adding C(c_k, k) for the k-th set bit at position c_k (the ctz loop of the
- * combinadics ranking figure, Sec. III.A).
+ * Combinadics rank, Eq. cns with Eq. rank: with the occupied orbitals in
+ * increasing position c_1 < c_2 < ... < c_N, the rank is the sum over k of
+ * C(c_k, k).  Summed position by position: k counts the occupied orbitals
+ * seen so far, and an occupied position adds C(position, k).
  */
 uint64_t orc_cns_rank(uint64_t a)
 {
-    uint64_t i = 0;
-    int k = 1;
-    while (a != 0) {
-        int c = __builtin_ctzll(a);
-        a &= a - 1;
-        i += orc_binom(c, k);
-        ++k;
+    uint64_t rank = 0;
+    int k = 0;
+    for (int pos = 0; pos < 64; ++pos) {
+        if ((a >> pos) & 1u) {
+            ++k;
+            rank += orc_binom(pos, k);
+        }
     }
-    return i;
+    return rank;
 }
 
 void orc_cns_rank_batch(const uint64_t *q, int64_t n, uint64_t *out)
@@ -267,4 +268,66 @@ int64_t orc_terms_coo(const uint64_t *states, int64_t n, int nt,
         }
     }
     return cnt;
+}
+
+/* ---------------------------------------------------------------------------
+ * Plain gather-form H x of a Hubbard-type Hamiltonian with every hop target
+ * ranked by bisection in the sector list: the method the paper measures its
+ * staggered and trie lookups against inside H v (Sec. V.B).  Used as the
+ * timed CPU baseline; its results are checked against orc_apply_terms_bra.
+ *
+ * H = -sum_b t_b sum_s (c+_{i s} c_{j s} + h.c.) + sum_i U_i n_{i up} n_{i dn}
+ *     + sum_{i s} eps_i n_{i s},  spin-down in bits 0..L-1, spin-up in L..2L-1.
+ * Row a of the bra form (Eq. Talpha2): the diagonal, plus for every bond and
+ * spin whose two orbitals differ in a, -t_b times (-1)^(occupied orbitals
+ * strictly between them, on a) times x at the rank of a with both flipped
+ * (Eq. cee: <a| c+_p c_q is non-zero for a_p = 1, a_q = 0).
+ * Rows row_begin .. row_end-1 go to y[0 ..]; nthreads > 1 splits them over
+ * OpenMP threads (static schedule).  Returns 0, or -(row + 1) if a target
+ * is missing from the list.
+ */
+int64_t orc_hubbard_bisect_apply(const uint64_t *states, int64_t n, int L, int nb,
+                                 const int32_t *bi, const int32_t *bj, const double *bt,
+                                 const double *eps, const double *U, const double *x, double *y,
+                                 int64_t row_begin, int64_t row_end, int nthreads)
+{
+    int64_t bad = 0;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads) reduction(min:bad)
+    for (int64_t i = row_begin; i < row_end; ++i) {
+        const uint64_t a = states[i];
+        double diag = 0.0;
+        for (int site = 0; site < L; ++site) {
+            const int dn = (int)((a >> site) & 1u), up = (int)((a >> (L + site)) & 1u);
+            diag += eps[site] * (dn + up) + U[site] * (dn & up);
+        }
+        double acc = diag * x[i];
+        for (int b = 0; b < nb; ++b) {
+            const int lo = bi[b] < bj[b] ? bi[b] : bj[b], hi = bi[b] < bj[b] ? bj[b] : bi[b];
+            for (int spin = 0; spin < 2; ++spin) {
+                const int off = spin * L;
+                const uint64_t pi = (uint64_t)1 << (off + lo), pj = (uint64_t)1 << (off + hi);
+                if (((a & pi) != 0) == ((a & pj) != 0)) continue;
+                uint64_t between = 0;
+                for (int k = lo + 1; k < hi; ++k) between |= (uint64_t)1 << (off + k);
+                const int64_t j = bisect(states, n, a ^ pi ^ pj);
+                if (j < 0) { bad = bad < -(i + 1) ? bad : -(i + 1); continue; }
+                const double sgn = (popc64(a & between) & 1) ? -1.0 : 1.0;
+                acc += -bt[b] * sgn * x[j];
+            }
+        }
+        y[i - row_begin] = acc;
+    }
+    return bad;
+}
+
+/* Bisection and combinadics ranks of n queries split over nthreads OpenMP
+ * threads (the rank baselines of the timing leg). */
+void orc_rank_batch_mt(const uint64_t *states, int64_t ns, const uint64_t *q, int64_t n,
+                       int64_t *out, int method, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int64_t j = 0; j < n; ++j)
+        out[j] = method == 0 ? bisect(states, ns, q[j]) : (int64_t)orc_cns_rank(q[j]);
 }

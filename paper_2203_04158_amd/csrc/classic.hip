@@ -2,9 +2,9 @@
 // (Sec. III, Sec. V.A):
 //  * bisection: the lower bound of the pattern in the sector's ascending state
 //    list, accepted when the entry equals the pattern (any sector);
-//  * combinadics ranking (Fig. algr, Eq. cns): for the k-th set bit from the
-//    least significant end, at position c_k, add C(c_k, k) (particle-number
-//    sectors C^M_N only).
+//  * combinadics ranking (Eq. cns, Sec. III.A): the sum of C(c_k, k) over the
+//    occupied positions c_1 < ... < c_N, taken position by position
+//    (particle-number sectors C^M_N only).
 // Both keep the batch layout of the other rankers: queries in, ranks out,
 // MBR_NOT_FOUND for patterns outside the sector.
 #include <memory>
@@ -86,11 +86,14 @@ __global__ void __launch_bounds__(kBlock) rank_cns_kernel(const P *__restrict__ 
         const bool ok = fits(x, M) && h == N;
         uint32_t r = 0;
         if (ok) {
-            // Fig. algr: walk the set bits from the least significant end
-            for (int k = 1; x; ++k) {
-                const int c = (sizeof(P) == 8) ? __ffsll((unsigned long long)x) - 1 : __ffs((uint32_t)x) - 1;
-                x &= x - 1;
-                r += tab[c * ld + k];
+            // Eq. cns position by position: k counts the occupied orbitals
+            // seen so far, and an occupied position c adds C(c, k); k <= N
+            // keeps every read inside the table
+            int k = 0;
+            for (int c = 0; c < M; ++c) {
+                const uint32_t occ = (uint32_t)(x >> c) & 1u;
+                k += (int)occ;
+                r += occ ? tab[c * ld + k] : 0u;
             }
         }
         out[j] = ok ? r : MBR_NOT_FOUND;

@@ -41,28 +41,40 @@ Tup creator(int i) {
     return t;
 }
 
-// Tuple of the product T_a T_b (T_b acts first), App. A.  Restated:
-//  * on the orbitals of m_b the state must equal r_b; T_b leaves them at l_b.
-//    T_a then demands r_a on m_a, so where the masks overlap l_b must equal
-//    r_a (else the product vanishes), and on m_a outside m_b the original
-//    state must already hold r_a:  r = r_b | (r_a & ~m_b);
-//  * afterwards m_a holds l_a and the rest of m_b still holds l_b:
-//    l = l_a | (l_b & ~m_a), and the flipped orbitals are x = l ^ r;
-//  * the sign of T_b counts alpha & s_b, that of T_a the intermediate state &
-//    s_a.  Outside m both states equal alpha, giving the mask (s_a ^ s_b) & ~m;
-//    inside m they are fixed (r, then r ^ x_b), so their parity is a constant
-//    folded into v.
+// One tuple applied to a ket (Eq. Talpha1): false when it annihilates alpha,
+// else the coefficient is multiplied by its signed prefactor and alpha moved to
+// its image.
+bool act_on(const Tup &t, uint64_t &alpha, double &coef) {
+    if ((alpha & t.m) != t.r) return false;
+    coef *= (__builtin_popcountll(alpha & t.s) & 1) ? -t.v : t.v;
+    alpha ^= t.x;
+    return true;
+}
+
+// Tuple of the product T_a T_b (T_b acts first), App. A, by running the one
+// pattern that can survive through both factors.  The product touches the
+// orbitals of m = m_a | m_b: on m_b a surviving pattern must hold r_b, and on
+// the rest of m_a, which T_b leaves alone, it must hold r_a; outside m it is
+// free.  The pattern holding exactly that (nothing outside m) is pushed
+// through T_b and then T_a: if either annihilates it the product vanishes,
+// otherwise its image is l and the accumulated coefficient is v.  Outside m
+// each factor sees the same occupations, so an orbital there changes the sign
+// once per factor whose sign mask holds it: s = (s_a ^ s_b) & ~m.
 Tup product(const Tup &a, const Tup &b) {
     Tup t;
-    const bool clash = ((a.r ^ b.l) & a.m & b.m) != 0;
     t.m = a.m | b.m;
     t.r = b.r | (a.r & ~b.m);
-    t.l = a.l | (b.l & ~a.m);
-    t.x = t.l ^ t.r;
     t.s = (a.s ^ b.s) & ~t.m;
-    const uint64_t before = t.r, between = t.r ^ b.x;  // the state inside m before T_b and before T_a
-    const int parity = (__builtin_popcountll(before & b.s) + __builtin_popcountll(between & a.s)) & 1;
-    t.v = clash ? 0.0 : (parity ? -a.v * b.v : a.v * b.v);
+    uint64_t state = t.r;
+    double coef = 1.0;
+    if (!act_on(b, state, coef) || !act_on(a, state, coef)) {
+        t.v = 0.0;
+        t.l = t.x = 0;
+        return t;
+    }
+    t.l = state;
+    t.x = t.l ^ t.r;
+    t.v = coef;
     return t;
 }
 

@@ -132,3 +132,49 @@ def test_lanczos_converges_to_lowest():
     a, b = LZ.lanczos(lambda v: A @ v, v0, s.size + 5, reorth=True, breakdown=1e-10)
     assert a.size <= s.size
     assert abs(LZ.tridiag_lowest(a, b) - want) < 1e-10
+
+
+@pytest.mark.parametrize("L,periodic", [(2, False), (3, True), (4, True), (6, True)])
+def test_bisect_gather_apply_matches_dense_cee(L, periodic):
+    """The plain bisection gather form (the timed baseline) against the dense
+    Eq. cee Hamiltonian at L <= 4 and against the tuple-built apply above."""
+    bonds = H.chain_bonds(L, 0.7, periodic) + ([(0, L - 1, -0.3)] if L > 3 else [])
+    U = list(np.linspace(4.0, 1.0, L))
+    eps = list(np.linspace(-0.3, 0.2, L))
+    Hd = H.dense_from_cee(L, bonds, U, eps) if L <= 4 else None
+    tl = H.terms(L, bonds, U, eps)
+    for nu in range(L + 1):
+        for nd in range(L + 1):
+            s = H.sector(L, nu, nd)
+            x = start_vector(nu * 13 + nd + 1, s.size)
+            y = H.apply_bisect(s, L, bonds, U, eps, x)
+            want, ab = H.apply(s, tl, x, with_abssum=True)
+            assert (np.abs(y - want) <= 64 * 2.0 ** -52 * ab + 1e-300).all()
+            if Hd is not None:
+                assert np.abs(y - _sector_block(Hd, s) @ x).max() < 1e-12
+
+
+def test_bisect_gather_apply_impurity_threads_and_rows():
+    eps_b, V = anderson_parameters(5, 5)
+    L = 6
+    eps = [-4.0] + list(eps_b)
+    U = [8.0] + [0.0] * 5
+    bonds = H.star_bonds(V)
+    tl = H.terms(L, bonds, U, eps)
+    s = H.sector(L, 3, 2)
+    x = start_vector(9, s.size)
+    y1 = H.apply_bisect(s, L, bonds, U, eps, x)
+    y4 = H.apply_bisect(s, L, bonds, U, eps, x, threads=4)
+    part = H.apply_bisect(s, L, bonds, U, eps, x, row_range=(17, 101), threads=3)
+    want, ab = H.apply(s, tl, x, with_abssum=True)
+    assert np.array_equal(y1, y4) and np.array_equal(part, y1[17:101])
+    assert (np.abs(y1 - want) <= 64 * 2.0 ** -52 * ab + 1e-300).all()
+
+
+def test_threaded_rank_batches_match():
+    st = C.sector_enumerate(16, C.constraints(16, 7))
+    q = np.concatenate([st[::3], np.arange(0, 1 << 17, 97, dtype=np.uint64)])
+    b = C.rank_batch_threads(st, q, "bisect", 4)
+    assert np.array_equal(b, C.bisect_rank(st, q))
+    m = st[::5]
+    assert np.array_equal(C.rank_batch_threads(st, m, "cns", 3), C.cns_rank_batch(m).astype(np.int64))
