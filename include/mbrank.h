@@ -283,6 +283,19 @@ mbr_status mbr_mlp_forward(const float *d_params, const uint32_t *d_q, int32_t B
 mbr_status mbr_mlp_gradients(const float *d_params, const uint32_t *d_q, const float *d_tgt,
                              int32_t B, float *d_grad, float *d_loss, void *stream);
 
+/* mbr_mlp_gradients without any device allocation and without host
+ * synchronisation, for callers that cannot allocate: a training step captured
+ * in a HIP graph, or a loop that may not call hipMalloc.  Same arguments,
+ * kernels and results as mbr_mlp_gradients; the scratch (rounded weights,
+ * per-sample activations, per-64-sample gradient partials) is one static
+ * device array of about 11.8 MB that each device holds until the process
+ * ends, sized for B <= 8192 (MBR_ERANGE beyond).  Every scratch word a call
+ * reads is written earlier in the same call, so nothing needs clearing, but
+ * calls that overlap on one device (other streams, other threads) share that
+ * array and race: serialise them.  Only enqueues work on `stream`. */
+mbr_status mbr_mlp_gradients_noalloc(const float *d_params, const uint32_t *d_q, const float *d_tgt,
+                                     int32_t B, float *d_grad, float *d_loss, void *stream);
+
 mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info);
 
 /* Rank n patterns: d_rank[j] = rank of d_q[j] in the ranker's sector or

@@ -131,6 +131,8 @@ _SIGS = {
     "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mbr_mlp_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_mlp_gradients_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_ranker_info_get": (C.c_int32, [C.c_void_p, C.POINTER(RankerInfo)]),
     "mbr_rank_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "mbr_ranker_destroy": (C.c_int32, [C.c_void_p]),
@@ -428,6 +430,16 @@ def mlp_gradients(params, q, target, stream=None):
     _check("mbr_mlp_gradients", lib().mbr_mlp_gradients(_dvec(params, 4, 6337, "params"), _dvec(q, 4, n, "q"),
                                                         _dvec(target, 4, n, "target"), n, _dptr(grad),
                                                         _dptr(loss), _stream(stream)))
+    return grad, loss
+
+
+def mlp_gradients_noalloc(params, q, target, grad, loss, stream=None):
+    """mbr_mlp_gradients into caller-provided grad[6337] and loss[1] (fp32
+    device tensors), with no allocation and no synchronisation in the library."""
+    n = q.numel()
+    _check("mbr_mlp_gradients_noalloc", lib().mbr_mlp_gradients_noalloc(
+        _dvec(params, 4, 6337, "params"), _dvec(q, 4, n, "q"), _dvec(target, 4, n, "target"), n,
+        _dvec(grad, 4, 6337, "grad"), _dvec(loss, 4, 1, "loss"), _stream(stream)))
     return grad, loss
 
 

@@ -31,6 +31,7 @@
 // weights, backward, fixed-order batch reductions, Adam).
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -594,6 +595,23 @@ __global__ void mlp_loss_kernel(const float *__restrict__ lp, int nparts, int B,
     *loss = s / (float)B;
 }
 
+// Bytes of a batch's activation scratch and of its chunk partials.
+constexpr size_t act_bytes(size_t b) { return b * 4 * (4 * kH + 2) + (b / 64 + 1) * 4; }
+constexpr size_t part_bytes(size_t b) { return (b + kChunk - 1) / kChunk * kParams * 4; }
+
+// Activation scratch of B samples laid out in the memory at f.
+TrainScratch carve(float *f, size_t n) {
+    TrainScratch S{};
+    S.h1 = f;
+    S.h2 = f + n * kH;
+    S.dz1 = f + 2 * n * kH;
+    S.dz2 = f + 3 * n * kH;
+    S.dy = f + 4 * n * kH;
+    S.x = reinterpret_cast<uint32_t *>(f + 4 * n * kH + n);
+    S.loss_part = f + 4 * n * kH + 2 * n;
+    return S;
+}
+
 // Batch scratch of B samples.
 struct TrainBufs {
     mbr::DevBuf scratch, part;
@@ -601,20 +619,48 @@ struct TrainBufs {
     int B = 0;
     mbr_status alloc(int b) {
         B = b;
-        const size_t n = (size_t)b;
-        MBR_TRY(scratch.alloc(n * 4 * (4 * kH + 2) + (n / 64 + 1) * 4));
-        float *f = scratch.as<float>();
-        S.h1 = f;
-        S.h2 = f + n * kH;
-        S.dz1 = f + 2 * n * kH;
-        S.dz2 = f + 3 * n * kH;
-        S.dy = f + 4 * n * kH;
-        S.x = reinterpret_cast<uint32_t *>(f + 4 * n * kH + n);
-        S.loss_part = f + 4 * n * kH + 2 * n;
-        MBR_TRY(part.alloc((size_t)((b + kChunk - 1) / kChunk) * kParams * 4));
+        MBR_TRY(scratch.alloc(act_bytes((size_t)b)));
+        S = carve(scratch.as<float>(), (size_t)b);
+        MBR_TRY(part.alloc(part_bytes((size_t)b)));
         return MBR_OK;
     }
 };
+
+// Scratch of mbr_mlp_gradients_noalloc in one file-scope device array: the
+// rounded weights (fp32 and bf16), then the activations and the chunk
+// partials of a batch of up to kStaticBatch samples.  Each device holds its
+// own copy for the life of the process; host code uses only the address
+// hipGetSymbolAddress returns for the current device (static_scratch).
+constexpr int kStaticBatch = 8192;
+constexpr size_t kAl = 256;
+constexpr size_t al256(size_t v) { return (v + kAl - 1) / kAl * kAl; }
+constexpr size_t kStWr = 0;
+constexpr size_t kStWb = al256(kStWr + (size_t)kParams * 4);
+constexpr size_t kStAct = al256(kStWb + (size_t)kParams * 2);
+constexpr size_t kStPart = al256(kStAct + act_bytes(kStaticBatch));
+constexpr size_t kStaticBytes = al256(kStPart + part_bytes(kStaticBatch));
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on the current device, looked up once per device.
+mbr_status static_scratch(unsigned char **out) {
+    int dev = 0;
+    MBR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) MBR_FAIL(MBR_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            MBR_FAIL(MBR_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_static_ptr[dev]);
+    return MBR_OK;
+}
 
 // Forward/backward and chunk partials of one batch.
 mbr_status batch_grad(TrainBufs &T, const float *wr, const uint32_t *q, const float *tgt,
@@ -916,6 +962,32 @@ mbr_status mbr_mlp_gradients(const float *d_params, const uint32_t *d_q, const f
     if (d_loss) mlp_loss_kernel<<<1, 1, 0, s>>>(T.S.loss_part, B / 64, B, d_loss);
     MBR_HIP(hipGetLastError());
     MBR_HIP(hipStreamSynchronize(s));
+    return MBR_OK;
+}
+
+mbr_status mbr_mlp_gradients_noalloc(const float *d_params, const uint32_t *d_q, const float *d_tgt, int32_t B,
+                                     float *d_grad, float *d_loss, void *stream) {
+    using namespace mbr;
+    if (!d_params || !d_q || !d_tgt || !d_grad) MBR_FAIL(MBR_EINVAL, "null pointer");
+    if (B <= 0 || B % 64 != 0) MBR_FAIL(MBR_EINVAL, "B=%d must be a positive multiple of 64", B);
+    if (B > kStaticBatch)
+        MBR_FAIL(MBR_ERANGE, "B=%d exceeds the %d samples of the static scratch", B, kStaticBatch);
+    unsigned char *base = nullptr;
+    MBR_TRY(static_scratch(&base));
+    hipStream_t s = as_stream(stream);
+    float *wr = reinterpret_cast<float *>(base + kStWr);
+    uint16_t *wb = reinterpret_cast<uint16_t *>(base + kStWb);
+    const TrainScratch S = carve(reinterpret_cast<float *>(base + kStAct), (size_t)B);
+    float *part = reinterpret_cast<float *>(base + kStPart);
+    // every scratch word the kernels read is written first in this call
+    mlp_round_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(d_params, wr, wb);
+    mlp_fwd_bwd_kernel<<<(B + 63) / 64, 64, 0, s>>>(wr, B, d_q, d_tgt, nullptr, 0, 0, 0, S);
+    mlp_grad_part_kernel<<<(B + kChunk - 1) / kChunk, 256, 0, s>>>(B, S, part);
+    mlp_reduce_adam_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(part, (B + kChunk - 1) / kChunk, d_grad, nullptr,
+                                                                 nullptr, nullptr, nullptr, nullptr, 0.f, 1.f, 1.f,
+                                                                 0);
+    if (d_loss) mlp_loss_kernel<<<1, 1, 0, s>>>(S.loss_part, B / 64, B, d_loss);
+    MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
 
