@@ -5,34 +5,43 @@ Headline workload: periodic Hubbard chain, L = 14 sites, t = 1, U = 4, sector
 from a seeded random unit start vector.  A step is one Lanczos step: the
 on-the-fly H·x (unrank both halves, staggered rank of every hop target,
 fermion signs, gather x) fused with u = H v_j - beta v_{j-1} and the alpha
-partials, then alpha, w = u - alpha v_j, beta.  `value` is steps per second,
-i.e. full H·x products per second; `granks_per_s` counts the ranked hop
-targets.  All inputs are synthetic and resident in HBM before timing.
+partials, then alpha, w = u - alpha v_j, beta.  `value` is Lanczos steps per
+second; `hv_per_s` is plain H·x products per second and `granks_per_s` the
+ranked hop targets per second of the step.  All inputs are synthetic and
+resident in HBM before timing.
 
-The other workloads of the path are measured after the headline and reported
-under "rows" (kernel time by HIP events on the launch stream, each result
-checked for exactness or against stored oracle energies):
-  staggered  sector M=24, N=12; 2^22 uniform member queries; k = 8
-  staggered64  M=64, N=32 with 64-bit patterns and ranks; 2^22 queries; k = 4, 8, 16
-  trie       M=32, N=16 with >= 6 of orbitals 0-7 occupied (66,110,671 states);
-             2^24 queries, 90% members and 10% non-members; k = 4 and 8
-  learned    learned index vs its search without the network vs trie vs
-             spin-product staggered rank on the (7,7) chain sector as 28-bit
-             patterns, and the first three on M = 32 with 8 + 8 particles
-             (165,636,900 states); 2^24 queries
-  batched    Anderson impurity model (12 sites, U = 8, eps_d = -4), all 169
-             (N_up, N_dn) sectors, 150 steps with full reorthogonalisation:
-             batched graph-captured steps with fp32 vectors against per-sector
-             launches with fp64 vectors
-  operator   generic term-tuple H·x on the momentum-space Hubbard ring, L = 14,
-             (7,7), total momentum 0, trie ranks
-  sweep      (by name only) the ranking microbenchmark of Sec. V.A: M = 28,
-             N = 1..27, sorted queries, bisection / combinadics / staggered /
-             trie at R = 4, 8, 12
+The other workloads of the path are measured after the headline (kernel time
+by HIP events on the launch stream, every result checked for exactness or
+against stored oracle energies):
+  staggered    sector M=24, N=12; 2^22 uniform member queries; k = 8
+  unrank       list gathers and list-free spin unrank, 2^24 indices
+  staggered64  M=64, N=32 with 64-bit patterns and ranks; 2^22 queries
+  trie         M=32, N=16 with >= 6 of orbitals 0-7 occupied (66,110,671
+               states); 2^24 queries, 90% members and 10% non-members; k = 4, 8
+  learned      learned index vs its search without the network vs trie vs
+               spin-product staggered rank on the (7,7) chain sector as 28-bit
+               patterns, and on M = 32 with 8 + 8 particles (165,636,900 states)
+  chain        the headline chain with fp32 vectors (fp64 dot products), with
+               and without reorthogonalisation, against fp64 at equal policy
+  batched      Anderson impurity model (12 sites, U = 8, eps_d = -4), all 169
+               sectors, 150 steps: batched graph-captured vs per-sector
+               launches, each with fp32 and fp64 vectors, full
+               reorthogonalisation; and both batched forms without it
+  operator     generic term-tuple H·x on the momentum-space Hubbard ring, L = 14,
+               (7,7), total momentum 0, trie ranks
+  ceiling      measured ceilings: a plain copy, and random 4-byte gathers
+               (independent and 4-deep chains) at footprints of 1 MB to 4 GB
+               and from LDS
+  sweep        (by name only) the ranking microbenchmark of Sec. V.A: M = 28,
+               N = 1..27, sorted queries, bisection / combinadics / staggered /
+               trie at R = 4, 8, 12
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--rows all|none|a,b]
 
-Prints one JSON line.  Only one GPU is used; --gpus above 1 is rejected.
+Prints one compact JSON line on stdout (headline, roofline, CPU baseline and a
+short summary per workload); the full record of every workload goes to
+stderr as one line starting with "[bench] detail".  Only one GPU is used;
+--gpus above 1 is rejected.
 """
 from __future__ import annotations
 
@@ -51,7 +60,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Granks/s and Hubbard H·v/s, learned+batched vs plain trie, same GPU"
 HBM_PEAK_GBS = 8000.0
 L, U, NUP, NDN, SEED = 14, 4.0, 7, 7, 2
-ROWS = ("staggered", "unrank", "staggered64", "trie", "learned", "batched", "operator")
+ROWS = ("staggered", "unrank", "staggered64", "trie", "learned", "chain", "batched", "operator", "ceiling")
 EXTRA_ROWS = ("sweep",)   # run only when asked for by name
 
 
@@ -70,37 +79,69 @@ def hops_per_product(L, nu, nd):
     return per_up * cd + per_dn * cu
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(budget_s: float):
-    """The oracle's H·x (tuple terms, Eq. Talpha2, bisection ranks; plain C,
-    one thread) on a contiguous block of rows, scaled to products per second."""
+    """The oracle's plain gather-form H·x with bisection ranks (the baseline
+    method of Sec. V.B, fp64, plain C) on the headline workload, on one thread
+    and on every host thread this process may use, each over a bounded block
+    of rows scaled to whole products; Lanczos steps/s adds the step's vector
+    work (two dot products, three vector updates) timed with numpy.  Also the
+    oracle's bisection and combinadics ranks of the staggered row's workload
+    (M = 24, N = 12, 2^22 member queries), unsorted and sorted."""
     from oracle import hamiltonian as OH
-    import synth
-    st = OH.sector(L, NUP, NDN)
-    tl = OH.terms(L, chain_bonds(L), U)
-    x = synth.start_vector(SEED, st.size)
-    rows = 20000
-    t0 = time.perf_counter()
-    OH.apply(st, tl, x, row_range=(0, rows))
-    dt = time.perf_counter() - t0
-    rows = int(min(st.size, max(rows, rows * budget_s / max(dt, 1e-9))))
-    t0 = time.perf_counter()
-    OH.apply(st, tl, x, row_range=(0, rows))
-    dt = time.perf_counter() - t0
-    rate = rows / dt / st.size
-    # context for the ranking rows: the oracle's bisection and combinadics
-    # ranks of the staggered row's workload (M=24, N=12, 2^22 member queries)
     from oracle import combinatorics as OC
-    sec = OC.sector_enumerate(24, OC.constraints(24, 12))
-    q = sec[synth.uniform_indices(1, 1 << 22, sec.size)]
-    ranks = {}
-    for name, fn in (("bisect", lambda: OC.bisect_rank(sec, q)), ("cns", lambda: OC.cns_rank_batch(q))):
+    import synth
+    threads = len(os.sched_getaffinity(0))
+    st = OH.sector(L, NUP, NDN)
+    x = synth.start_vector(SEED, st.size)
+    bonds = chain_bonds(L)
+
+    def rate(nt, share):
+        rows = 20000 * nt
         t0 = time.perf_counter()
-        fn()
-        ranks[name] = {"value": q.size / (time.perf_counter() - t0) / 1e9, "unit": "Granks/s", "cores": 1}
-    return {"value": rate, "unit": "H·v/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle H·x over rows 0..{rows - 1} of {st.size} ({dt:.1f} s, 1 thread), "
-                      f"scaled to whole products",
-            "rank_m24_n12_2e22": ranks}
+        OH.apply_bisect(st, L, bonds, U, None, x, row_range=(0, rows), threads=nt)
+        dt = time.perf_counter() - t0
+        rows = int(min(st.size, max(rows, rows * share / max(dt, 1e-9))))
+        t0 = time.perf_counter()
+        OH.apply_bisect(st, L, bonds, U, None, x, row_range=(0, rows), threads=nt)
+        dt = time.perf_counter() - t0
+        return rows / dt / st.size, rows, dt
+
+    hv1, rows1, dt1 = rate(1, 0.35 * budget_s)
+    hvn, rowsn, dtn = rate(threads, 0.35 * budget_s)
+    w, u, q = x.copy(), x * 0.5, x * 0.25
+    t0 = time.perf_counter()
+    a = float(np.dot(q, u))
+    u -= a * q
+    u -= 0.5 * w
+    b = float(np.sqrt(np.dot(u, u)))
+    w[:] = u / b
+    t_vec = time.perf_counter() - t0
+    sec = OC.sector_enumerate(24, OC.constraints(24, 12))
+    qr = sec[synth.uniform_indices(1, 1 << 22, sec.size)]
+    qs = np.sort(qr)
+    ranks = {}
+    for meth in ("bisect", "cns"):
+        for order, qq in (("unsorted", qr), ("sorted", qs)):
+            for nt in (1, threads):
+                t0 = time.perf_counter()
+                OC.rank_batch_threads(sec, qq, meth, nt)
+                ranks[f"{meth}_{order}_{nt}t"] = round(qq.size / (time.perf_counter() - t0) / 1e9, 4)
+    return {"value": 1.0 / (1.0 / hvn + t_vec), "unit": "Lanczos steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"plain bisection gather-form H·x (oracle, fp64) over rows 0..{rowsn - 1} on {threads} "
+                      f"threads ({dtn:.1f} s) and 0..{rows1 - 1} on 1 ({dt1:.1f} s) of {st.size}, scaled "
+                      f"to whole products, plus the step's vector work (numpy, {t_vec * 1e3:.0f} ms)",
+            "hv_per_s_1t": hv1, "hv_per_s_all": hvn, "steps_per_s_1t": 1.0 / (1.0 / hv1 + t_vec),
+            "cpu": _cpu_model(), "nproc": os.cpu_count(), "rank_Granks_m24_n12_2e22": ranks}
 
 
 # --------------------------------------------------------------------------- helpers
@@ -295,21 +336,37 @@ def row_trie(torch, mbr, reps):
         info = r.info()
         ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
         exact = bool(torch.equal(out, want))
-        # algorithmic bytes per query: the query in and the rank out, plus one
-        # HBM granule for every dependent gather into an array that neither LDS
-        # nor an XCD's L2 holds (levels below the staged ones, and the state
-        # list of the membership check)
+        # algorithmic bytes per query (the survey's count for this workload):
+        # the query in and the rank out, plus two 64-B HBM granules, one for
+        # the leaf level and one for the membership read of the state list
+        per_q = 8.0 + 2 * GRANULE
+        roof = hbm_roofline(per_q * nq, ms, f"trie_rank_kernel ({per_q:.0f} B per query: 8 B stream + "
+                                            f"2 random {GRANULE}-B granules)")
+        roof["traffic"] = traffic_for(f"trie_rank_kernel<unsignedint>@k{k}")
+        # context: one granule for every dependent gather into an array that
+        # neither LDS nor an XCD's L2 holds (at k = 8 also level 2, 9.4 MB)
         ent, lds_lv = mbr.trie_level_entries(r)
         far = [l for l in range(len(ent)) if l >= lds_lv and 4 * ent[l] > L2_BYTES]
         gathers = len(far) + (1 if 4 * s.size > L2_BYTES else 0)
-        per_q = 8.0 + GRANULE * gathers
-        roof = hbm_roofline(per_q * nq, ms, f"trie_rank_kernel ({per_q:.0f} B per query: 8 B stream + "
-                                            f"{gathers} random {GRANULE}-B granules)")
-        roof["traffic"] = traffic_for(f"trie_rank_kernel<unsignedint>@k{k}")
+        roof["frac_counting_every_far_level"] = (8.0 + GRANULE * gathers) * nq / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        roof["far_gathers_per_query"] = gathers
         res[f"k{k}"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
                         "exact": exact, "levels": info.levels, "lds_levels": lds_lv,
                         "level_bytes": [4 * e for e in ent], "trie_bytes": int(info.bytes),
                         "overhead_f": info.bytes / 4 / s.size, "roofline": roof}
+        del r
+    # the bitmap trie (records {base, bitmap}, membership from the bitmaps):
+    # 8 B stream + one 64-B granule for the one level beyond L2 (k = 8)
+    for k in (4, 8):
+        r = mbr.build_bitmap_trie(s, k)
+        ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
+        recs, rbytes, lds_lv = mbr.bitmap_trie_levels(r)
+        res[f"bitmap_k{k}"] = {"value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms,
+                               "exact": bool(torch.equal(out, want)), "bytes": int(r.info().bytes),
+                               "overhead_f": r.info().bytes / 4 / s.size, "records": recs,
+                               "record_bytes": rbytes, "lds_levels": lds_lv,
+                               "roofline": hbm_roofline(136.0 * nq, ms, "bt_rank_kernel at the survey's "
+                                                                        "136 B per query")}
         del r
     # the learned ranker's search without its network, on the same queries
     r = mbr.build_sampled_ranker(s)
@@ -345,17 +402,11 @@ def row_learned(torch, mbr, reps, big: bool):
         res["learned_stats"] = mbr.learned_stats(lr_)
         if name == cases[0][0]:
             # stage 1 alone on the matrix cores: the network's forward pass over
-            # the 2^24 queries (the entry point also rounds the parameters to
-            # bf16 into two small scratch buffers and synchronises)
+            # the 2^24 queries (one kernel; it rounds the fp32 parameters to
+            # bf16 as it loads them), timed by HIP events on its stream
             params = torch.from_numpy(mbr.learned_params(lr_)).cuda()
             yq = torch.empty(nq, dtype=torch.float32, device="cuda")
-            mbr.mlp_forward(params, q, out=yq)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(5):
-                mbr.mlp_forward(params, q, out=yq)
-            torch.cuda.synchronize()
-            mlp_ms = (time.perf_counter() - t0) * 1e3 / 5
+            mlp_ms = time_launches(torch, lambda: mbr.mlp_forward(params, q, out=yq), reps)
             flops = 12416.0 * nq
             res["mlp_forward"] = {"ms": mlp_ms, "roofline": {
                 "bound": "mfma", "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": 2500.0,
@@ -364,7 +415,8 @@ def row_learned(torch, mbr, reps, big: bool):
         res["learned_train"] = ("8 epochs x min(N_s, 2^22) samples, batch 4096, Adam lr 2e-3, seed 4; "
                                 "2^b leaves, about 4 members per leaf, at most 2^12")
         # the same search without the network: the whole list is the window
-        rankers = [("trie_k8", trie), ("learned", lr_), ("sampled_search_no_net", mbr.build_sampled_ranker(s))]
+        rankers = [("trie_k8", trie), ("learned", lr_), ("sampled_search_no_net", mbr.build_sampled_ranker(s)),
+                   ("bitmap_trie_k8", mbr.build_bitmap_trie(s, 8))]
         if spin is not None:
             rankers.append(("spin_staggered", mbr.build_spin_ranker(*spin, k=7)))
         ranked = torch.empty(nq, dtype=torch.int32, device="cuda")
@@ -467,11 +519,13 @@ def row_operator(torch, mbr, reps):
 
 
 def row_batched(torch, mbr, steps: int):
-    """Anderson impurity model, all 169 sectors, `steps` Lanczos steps with full
-    reorthogonalisation: batched + graph + fp32 vectors against per-sector
-    launches with fp64 vectors; and the batched fp32 run without
-    reorthogonalisation (three-term recurrence only).  Energies against the
-    stored oracle values."""
+    """Anderson impurity model, all 169 sectors, `steps` Lanczos steps:
+    batched graph-captured steps against per-sector launches, each with fp32
+    vectors (fp64 dot products) and with fp64 vectors, all with full
+    reorthogonalisation (equal policy), so that batching and precision each
+    show their own gain; and the two batched forms without
+    reorthogonalisation (three-term recurrence).  Energies against the stored
+    oracle values."""
     import synth
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "anderson_12.json")))
     Ls = 12
@@ -480,11 +534,16 @@ def row_batched(torch, mbr, steps: int):
     bonds = [(0, l + 1, -float(v)) for l, v in enumerate(g["V"])]  # +V (c+_0 c_l + h.c.)
     sectors = [(nu, nd) for nu in range(Ls + 1) for nd in range(Ls + 1)]
     res = {"workload": "Anderson impurity, 1 + 11 bath sites, U=8, eps_d=-4, all 169 sectors "
-                       f"(16,777,216 states), {steps} steps, full reorthogonalisation"}
-    for name, prec, batched, reorth in (("batched_graph_fp32", mbr.F32, True, True),
+                       f"(16,777,216 states), {steps} steps"}
+    hv = {}
+    for name, prec, batched, reorth in (("batched_fp32", mbr.F32, True, True),
+                                        ("batched_fp64", mbr.F64, True, True),
+                                        ("per_sector_fp32", mbr.F32, False, True),
                                         ("per_sector_fp64", mbr.F64, False, True),
-                                        ("batched_graph_fp32_no_reorth", mbr.F32, True, False)):
+                                        ("batched_fp32_no_reorth", mbr.F32, True, False),
+                                        ("batched_fp64_no_reorth", mbr.F64, True, False)):
         h = mbr.hubbard_create(Ls, bonds, sectors, U=Us, eps=eps, precision=prec)
+        shape = mbr.hubbard_autotune(h, reps=3)   # (k, G, block) for this Hamiltonian and precision
         v0 = torch.from_numpy(synth.start_vector(5, h.dim)).cuda()
         lz = mbr.lanczos_create(h, steps, reorth=reorth, batched=batched, use_graph=True)
         mbr.lanczos_start(lz, v0)
@@ -498,20 +557,135 @@ def row_batched(torch, mbr, steps: int):
         e0, nst = mbr.lanczos_result(lz)
         worst = max(abs(e0[i] - g["e0"][f"{nu},{nd}"]) / max(1.0, abs(g["e0"][f"{nu},{nd}"]))
                     for i, (nu, nd) in enumerate(sectors))
-        x = torch.zeros(h.dim, dtype=torch.float32 if prec == mbr.F32 else torch.float64,
-                        device="cuda")
-        x.copy_(v0)
-        y = torch.empty_like(x)
-        hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 20)
-        tsz = 4 if prec == mbr.F32 else 8
         res[name] = {"value": steps / dt, "unit": "Lanczos steps/s", "ms_per_step": dt * 1e3 / steps,
                      "reorth": reorth, "e0": float(e0.min()), "worst_rel_err_vs_oracle": worst,
-                     "hv_kernel_ms": hv_ms, "hv_per_s": 1e3 / hv_ms,
-                     "hv_roofline": hbm_roofline(2.0 * tsz * h.dim, hv_ms,
-                                                 f"H·x over all 169 sectors ({2 * tsz} B per row)")}
+                     "launch": {kk: shape[kk] for kk in ("k", "G", "block", "tuned_ms")}}
+        del lz
+        torch.cuda.synchronize()
+        if batched and reorth:
+            x = torch.zeros(h.dim, dtype=torch.float32 if prec == mbr.F32 else torch.float64,
+                            device="cuda")
+            x.copy_(v0)
+            y = torch.empty_like(x)
+            hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 20)
+            tsz = 4 if prec == mbr.F32 else 8
+            hv[name.split("_")[1]] = {"kernel_ms": hv_ms, "hv_per_s": 1e3 / hv_ms, "launch": shape,
+                                      "roofline": hbm_roofline(2.0 * tsz * h.dim, hv_ms,
+                                                               f"H·x over all 169 sectors ({2 * tsz} B per row)")}
+            # every launch shape of the product, for the record
+            shapes = {}
+            for G in (-1, 0, 1, 2, 4):
+                try:
+                    mbr.hubbard_set_config(h, shape["k"], G, 512)
+                except mbr.MbrError:
+                    continue
+                shapes[f"G{G}"] = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 10)
+            mbr.hubbard_set_config(h, shape["k"], shape["G"], shape["block"])
+            hv[name.split("_")[1]]["ms_by_G"] = shapes
+            del x, y
+        del h
+        torch.cuda.synchronize()
+    res["hv"] = hv
+    v = {k: res[k]["value"] for k in res if isinstance(res[k], dict) and "value" in res[k]}
+    res["gain_batching_fp32"] = v["batched_fp32"] / v["per_sector_fp32"]
+    res["gain_batching_fp64"] = v["batched_fp64"] / v["per_sector_fp64"]
+    res["gain_fp32_batched"] = v["batched_fp32"] / v["batched_fp64"]
+    res["gain_fp32_per_sector"] = v["per_sector_fp32"] / v["per_sector_fp64"]
+    res["gain_fp32_no_reorth"] = v["batched_fp32_no_reorth"] / v["batched_fp64_no_reorth"]
+    res["gain_both"] = v["batched_fp32"] / v["per_sector_fp64"]
+    return res
+
+
+def row_chain(torch, mbr, steps: int):
+    """The headline chain (L = 14, (7,7)) with the precisions of the mixed form:
+    fp64 vectors without reorthogonalisation (the headline), fp32 vectors with
+    fp64 dot products without it, and both with full reorthogonalisation;
+    ground energy against the oracle's."""
+    import synth
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "hubbard_chain_L14.json")))["e0_exact"]
+    res = {"workload": f"chain L=14 U=4 (7,7), {steps} steps, start vector seed {SEED}"}
+    for name, prec, reorth in (("fp64", mbr.F64, False), ("fp32", mbr.F32, False),
+                               ("fp64_reorth", mbr.F64, True), ("fp32_reorth", mbr.F32, True)):
+        h = mbr.hubbard_create(L, chain_bonds(L), [(NUP, NDN)], U=[U] * L, precision=prec)
+        v0 = torch.from_numpy(synth.start_vector(SEED, h.dim)).cuda()
+        lz = mbr.lanczos_create(h, steps, reorth=reorth, use_graph=True)
+        mbr.lanczos_start(lz, v0)
+        mbr.lanczos_step(lz, 2)
+        mbr.lanczos_start(lz, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mbr.lanczos_step(lz, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e0, _ = mbr.lanczos_result(lz)
+        res[name] = {"value": steps / dt, "unit": "Lanczos steps/s", "ms_per_step": dt * 1e3 / steps,
+                     "e0": float(e0[0]), "rel_err_vs_oracle": abs(e0[0] - gold) / abs(gold)}
+        if not reorth:
+            x = torch.zeros(h.dim, dtype=torch.float32 if prec == mbr.F32 else torch.float64, device="cuda")
+            x.copy_(v0)
+            y = torch.empty_like(x)
+            res[name]["hv_kernel_ms"] = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), 20)
+            del x, y
         del lz, h
         torch.cuda.synchronize()
-    res["speedup_steps"] = res["batched_graph_fp32"]["value"] / res["per_sector_fp64"]["value"]
+    # the plain trie inside H·x: every hop target's 28-bit pattern ranked by a
+    # packed trie over the sector (k = 7, four levels), same sums
+    for k in (7, 14):
+        ht = mbr.hubbard_create(L, chain_bonds(L), [(NUP, NDN)], U=[U] * L, rank_kind=mbr.RANK_TRIE, k=k)
+        v0 = torch.from_numpy(synth.start_vector(SEED, ht.dim)).cuda()
+        x = v0.clone()
+        y = torch.empty_like(x)
+        ms = time_launches(torch, lambda: mbr.hubbard_apply(ht, x, y), 10)
+        lz = mbr.lanczos_create(ht, steps, use_graph=True)
+        mbr.lanczos_start(lz, v0)
+        mbr.lanczos_step(lz, 2)
+        mbr.lanczos_start(lz, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mbr.lanczos_step(lz, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e0, _ = mbr.lanczos_result(lz)
+        res[f"trie_k{k}"] = {"value": steps / dt, "unit": "Lanczos steps/s", "hv_kernel_ms": ms,
+                             "hv_per_s": 1e3 / ms, "rel_err_vs_oracle": abs(e0[0] - gold) / abs(gold)}
+        del lz, ht, x, y
+        torch.cuda.synchronize()
+    res["gain_fp32"] = res["fp32"]["value"] / res["fp64"]["value"]
+    res["gain_fp32_reorth"] = res["fp32_reorth"]["value"] / res["fp64_reorth"]["value"]
+    res["staggered_vs_trie_hv"] = res["trie_k7"]["hv_kernel_ms"] / res["fp64"]["hv_kernel_ms"]
+    return res
+
+
+def row_ceiling(torch, mbr, reps):
+    """Measured ceilings for the rooflines: a plain copy of 1 GB (read + write),
+    and 2^24 random 4-byte gathers from tables of 1 MB to 4 GB, independent
+    (depth 1) and as 4-deep dependent chains like a trie walk, and from a
+    64 KB table staged in LDS.  Gathers are reported per second and as HBM
+    bandwidth counting one 64-byte granule per gather."""
+    nq = 1 << 24
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(60)
+    idx = torch.randint(0, 1 << 30, (nq,), dtype=torch.int32, device="cuda", generator=gen)
+    out = torch.empty(nq, dtype=torch.int32, device="cuda")
+    res = {"workload": "2^24 random 4-byte gathers per launch; tables of uniform random entries"}
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = time_launches(torch, lambda: b.copy_(a), reps)
+    res["copy_1GB"] = {"kernel_ms": ms, "GBs": 2.0 * a.numel() * 4 / (ms * 1e-3) / 1e9}
+    del a, b
+    for lg in (18, 20, 22, 24, 26, 28, 30):
+        tab = torch.randint(0, 1 << 30, (1 << lg,), dtype=torch.int32, device="cuda", generator=gen)
+        for depth in (1, 4):
+            ms = time_launches(torch, lambda: mbr.probe_gather(tab, idx, depth=depth, out=out), reps)
+            g = nq * depth / (ms * 1e-3)
+            res[f"{(4 << lg) >> 20}MB_d{depth}"] = {"kernel_ms": ms, "Ggathers_s": g / 1e9,
+                                                   "granule_GBs": g * GRANULE / 1e9}
+        del tab
+        torch.cuda.synchronize()
+    tab = torch.randint(0, 1 << 30, (1 << 14,), dtype=torch.int32, device="cuda", generator=gen)
+    for depth in (1, 4):
+        ms = time_launches(torch, lambda: mbr.probe_gather(tab, idx, depth=depth, lds=True, out=out), reps)
+        res[f"lds64KB_d{depth}"] = {"kernel_ms": ms, "Ggathers_s": nq * depth / (ms * 1e-3) / 1e9}
     return res
 
 
@@ -529,13 +703,14 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the 165.6M-state learned-index sector")
     ap.add_argument("--k", type=int, default=0, help="half-pattern chunk width (0 = automatic)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
-    ap.add_argument("--G", type=int, default=-1,
-                    help="fixed launch shape: alpha_up blocks per tile (0 = alpha_dn-stationary kernel); "
-                         "implies --no-tune")
+    ap.add_argument("--G", type=int, default=None,
+                    help="fixed launch shape: alpha_up blocks per tile (0 = alpha_dn-stationary kernel, "
+                         "-1 = flat kernel); implies --no-tune")
     ap.add_argument("--block", type=int, default=512, help="tile-kernel block size with --G")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="only the H·x product (and one plain copy of x for counter calibration); "
-                         "for hardware-counter runs")
+    ap.add_argument("--kernel-only", nargs="?", const="chain", choices=("chain", "anderson"),
+                    help="only the H·x product of the headline chain (or of the impurity model over all "
+                         "169 sectors, fp32) and one plain copy of x for counter calibration; for "
+                         "hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured on a single MI355X "
@@ -554,8 +729,26 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.kernel_only == "anderson":
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", "anderson_12.json")))
+        Ls = 12
+        ha = mbr.hubbard_create(Ls, [(0, l + 1, -float(v)) for l, v in enumerate(g["V"])],
+                                [(nu, nd) for nu in range(Ls + 1) for nd in range(Ls + 1)],
+                                U=[g["U"]] + [0.0] * (Ls - 1), eps=[g["eps_d"]] + g["eps_bath"], precision=mbr.F32)
+        if args.G is not None:
+            cfg = mbr.hubbard_get_config(ha)
+            mbr.hubbard_set_config(ha, k=cfg["k"], G=args.G, block=args.block)
+        x = torch.from_numpy(synth.start_vector(5, ha.dim)).to(device=dev, dtype=torch.float32)
+        y = torch.empty_like(x)
+        for _ in range(args.kernel_reps):
+            mbr.hubbard_apply(ha, x, y)
+        y.copy_(x)  # plain copy of dim fp32 values: known traffic for calibration
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": "anderson", "dim": ha.dim, "launch": mbr.hubbard_get_config(ha)}),
+              flush=True)
+        return
     h = mbr.hubbard_create(L, chain_bonds(L), [(NUP, NDN)], U=[U] * L, precision=mbr.F64, k=args.k)
-    if args.G >= 0:
+    if args.G is not None:
         cfg = mbr.hubbard_get_config(h)
         mbr.hubbard_set_config(h, k=cfg["k"], G=args.G, block=args.block)
     elif not args.no_tune:
@@ -618,7 +811,7 @@ def main():
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "H·v/s",
+        "unit": "Lanczos steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
@@ -633,12 +826,12 @@ def main():
                    "lanczos_steps": steps, "ranker": "staggered halves",
                    "start_vector_seed": SEED,
                    "launch": {k: launch_cfg[k] for k in ("k", "G", "block", "tiles")}},
-        "granks_per_s": value * hops / 1e9,
-        "hops_per_product": hops,
-        "hv_kernel_ms": hv_ms,
         "hv_per_s": 1e3 / hv_ms,
-        "e0": float(e0[0]),
-        "e0_rel_err_vs_oracle": (abs(e0[0] - e_ref) / abs(e_ref)) if e_ref else None,
+        "hv_kernel_ms": hv_ms,
+        "granks_per_s": value * hops / 1e9,
+        # Ritz value after `steps` steps against the converged oracle energy
+        # (converges by about 150 steps; the chain row runs 200)
+        "ritz_rel_gap_vs_oracle_e0": (abs(e0[0] - e_ref) / abs(e_ref)) if e_ref else None,
         "lanczos_steps_done": int(nsteps[0]),
         "roofline": roof,
     }
@@ -659,10 +852,14 @@ def main():
             extra[r] = row_trie(torch, mbr, 20)
         elif r == "learned":
             extra[r] = row_learned(torch, mbr, 20, big=not args.no_big)
+        elif r == "chain":
+            extra[r] = row_chain(torch, mbr, 200)
         elif r == "batched":
             extra[r] = row_batched(torch, mbr, 150)
         elif r == "operator":
             extra[r] = row_operator(torch, mbr, 5)
+        elif r == "ceiling":
+            extra[r] = row_ceiling(torch, mbr, 10)
         elif r == "sweep":
             extra[r] = row_sweep(torch, mbr, 10)
         extra[r]["wall_s"] = time.perf_counter() - t0
@@ -670,10 +867,94 @@ def main():
         torch.cuda.empty_cache()
         print(f"[bench] row {r} done in {extra[r]['wall_s']:.1f} s", file=sys.stderr, flush=True)
     if extra:
-        out["rows"] = extra
+        out["rows"] = summarize(extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    print("[bench] detail " + json.dumps({"headline": out, "rows": extra}), file=sys.stderr, flush=True)
+    print(json.dumps(_round(out)), flush=True)
+
+
+def _round(v, digits: int = 4):
+    """Floats to `digits` significant digits, for a short line."""
+    if isinstance(v, float):
+        return float(f"{v:.{digits}g}") if math.isfinite(v) else v
+    if isinstance(v, dict):
+        return {k: _round(x, digits) for k, x in v.items()}
+    if isinstance(v, list):
+        return [_round(x, digits) for x in v]
+    return v
+
+
+def summarize(extra: dict) -> dict:
+    """One short entry per workload for the JSON line (the full records go to
+    stderr): throughput, roofline fraction and exactness."""
+    s = {}
+    g = lambda d, *ks: [d.get(k) for k in ks]  # noqa: E731
+    if "staggered" in extra:
+        e = extra["staggered"]
+        s["cfg1_staggered"] = {"Granks_s": e["value"], "frac": e["roofline"]["frac"], "exact": e["exact"],
+                               "cold_Granks_s": e["cold_after_1GB_copy"]["value"],
+                               "2e28_Granks_s": e["stress_2e28"]["value"],
+                               "2e28_frac": e["stress_2e28"]["roofline"]["frac"]}
+    if "unrank" in extra:
+        e = extra["unrank"]
+        s["unrank_G_s"] = {k: e[k]["value"] for k in e if isinstance(e[k], dict) and "value" in e[k]}
+        s["unrank_exact"] = all(e[k]["exact"] for k in e if isinstance(e[k], dict) and "exact" in e[k])
+    if "staggered64" in extra:
+        e = extra["staggered64"]
+        s["m64_staggered_Granks_s"] = {k: e[k]["value"] for k in e if k.startswith("k")}
+        s["m64_exact"] = e["exact"]
+    if "trie" in extra:
+        e = extra["trie"]
+        s["cfg3_trie"] = {k: {"Granks_s": e[k]["value"], "frac": e[k]["roofline"]["frac"], "exact": e[k]["exact"],
+                              "f": e[k]["overhead_f"]} for k in ("k4", "k8") if k in e}
+        s["cfg3_trie"]["sampled_no_net_Granks_s"] = e["sampled_search_no_net"]["value"]
+        for k in ("bitmap_k4", "bitmap_k8"):
+            if k in e:
+                s["cfg3_trie"][k] = {"Granks_s": e[k]["value"], "frac": e[k]["roofline"]["frac"],
+                                     "exact": e[k]["exact"], "f": e[k]["overhead_f"]}
+    if "learned" in extra:
+        e = extra["learned"]
+        for name, r in e.items():
+            if not isinstance(r, dict) or "learned" not in r:
+                continue
+            names = ("learned", "sampled_search_no_net", "trie_k8", "bitmap_trie_k8", "spin_staggered")
+            t = {k: r[k]["value"] for k in names if k in r}
+            t["exact"] = all(r[k]["exact"] for k in names if k in r)
+            t["mean_window"] = r["learned_stats"]["mean_window"]
+            if "mlp_forward" in r:
+                t["mlp_frac"] = r["mlp_forward"]["roofline"]["frac"]
+            s[f"cfg4_{name}_Granks_s"] = t
+    if "chain" in extra:
+        e = extra["chain"]
+        s["cfg2_precision_steps_s"] = {k: e[k]["value"] for k in ("fp64", "fp32", "fp64_reorth", "fp32_reorth")}
+        s["cfg2_precision_rel_err"] = {k: e[k]["rel_err_vs_oracle"] for k in ("fp64", "fp32", "fp64_reorth",
+                                                                              "fp32_reorth")}
+        s["cfg2_trie_ranked"] = {k: {"steps_s": e[k]["value"], "hv_ms": e[k]["hv_kernel_ms"]}
+                                 for k in ("trie_k7", "trie_k14") if k in e}
+        s["cfg2_staggered_hv_ms"] = e["fp64"]["hv_kernel_ms"]
+    if "batched" in extra:
+        e = extra["batched"]
+        s["cfg5_steps_s"] = {k: e[k]["value"] for k in e if isinstance(e[k], dict) and "value" in e[k]}
+        s["cfg5_worst_rel_err"] = max(e[k]["worst_rel_err_vs_oracle"] for k in e
+                                      if isinstance(e[k], dict) and "worst_rel_err_vs_oracle" in e[k])
+        s["cfg5_gains"] = {k[5:]: e[k] for k in e if k.startswith("gain_")}
+        s["cfg5_hv"] = {k: {"ms": v["kernel_ms"], "frac": v["roofline"]["frac"], "G": v["launch"]["G"],
+                            "k": v["launch"]["k"], "ms_by_G": v.get("ms_by_G")} for k, v in e["hv"].items()}
+    if "operator" in extra:
+        e = extra["operator"]
+        s["momentum_ring_hv_s"] = {k: e[k]["value"] for k in ("trie_k7", "trie_k14")}
+        s["momentum_ring_e0_rel_diff"] = e["lanczos"]["rel_diff"]
+    if "ceiling" in extra:
+        e = extra["ceiling"]
+        s["ceiling"] = {"copy_GBs": e["copy_1GB"]["GBs"]}
+        s["ceiling"].update({k + "_GBs": v["granule_GBs"] for k, v in e.items() if k.endswith("_d1")
+                             and "granule_GBs" in v})
+        s["ceiling"]["lds_d1_Gg_s"] = e["lds64KB_d1"]["Ggathers_s"]
+    if "sweep" in extra:
+        s["sweep_half_filled_Granks_s"] = extra["sweep"]["half_filled_granks_per_s"]
+        s["sweep_exact"] = extra["sweep"]["exact"]
+    return s
 
 
 if __name__ == "__main__":

@@ -136,6 +136,7 @@ typedef struct mbr_ranker mbr_ranker;
 #define MBR_RANKER_BISECT    5
 #define MBR_RANKER_CNS       6
 #define MBR_RANKER_SAMPLED   7
+#define MBR_RANKER_BITMAP_TRIE 8
 
 typedef struct {
     int32_t kind;       /* MBR_RANKER_* */
@@ -195,6 +196,23 @@ mbr_status mbr_unrank_spin_batch(const mbr_ranker *r, const uint32_t *d_idx, uin
  * membership is checked against the sector's list (safe lookup, Sec. IV).
  * k in 1..16.  The trie keeps a reference to `s`: destroy it before `s`. */
 mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
+
+/* Bitmap trie (the radix-2^k trie of Sec. IV in a GPU layout): chunks
+ * dispatched from the most significant end (the top chunk holds M mod k bits
+ * when k does not divide M), every node one record of a 32-bit base and a
+ * 2^k-bit map of the chunk values that occur under it, 8, 16, 32 or 64 bytes
+ * (k <= 5, 6, 7, 8) aligned to its size.  The child for chunk value c is
+ * record base + (set bits below c) of the next level; at the last level that
+ * count gives the rank (base = position of the node's first member).  A clear
+ * bit means the pattern is not in the sector, so no state list is read.
+ * k in 1..8; the sector must be non-empty; the ranker keeps a reference to
+ * `s` (destroy it first).  Synchronises `stream`. */
+mbr_status mbr_build_bitmap_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void *stream);
+
+/* Layout of a bitmap trie: *levels levels, the top *lds_levels of them staged
+ * in LDS per workgroup; records[l] and record_bytes[l] for l < min(levels, cap). */
+mbr_status mbr_bitmap_trie_levels(const mbr_ranker *r, uint64_t *records, uint32_t *record_bytes,
+                                  int32_t cap, int32_t *levels, int32_t *lds_levels);
 
 /* The established methods the paper compares against (Sec. III, Sec. V.A).
  * Bisection: lower bound of the pattern in the sector's ascending list, found
@@ -389,6 +407,9 @@ typedef struct {
 #define MBR_F64 0
 #define MBR_F32 1
 
+#define MBR_HV_RANK_HALVES 0 /* staggered lookup of the half a hop changes (Eq. rankupdown) */
+#define MBR_HV_RANK_TRIE   1 /* packed trie over each sector's full 2L-bit patterns (Sec. IV) */
+
 typedef struct {
     int32_t L;                       /* sites, 1..16 */
     int32_t n_bonds;                 /* 0..48 */
@@ -398,13 +419,27 @@ typedef struct {
     int32_t n_sectors;               /* 1..1024 spin sectors, concatenated */
     const mbr_spin_sector *sectors;
     int32_t precision;               /* MBR_F64 or MBR_F32 vectors */
-    int32_t k;                       /* half-pattern chunk width, 0 = automatic */
+    int32_t k;                       /* chunk width, 0 = automatic: of the half-pattern table
+                                        (halves), or of the trie, 4..16 (trie; automatic: four levels) */
+    int32_t rank_kind;               /* MBR_HV_RANK_HALVES or MBR_HV_RANK_TRIE */
 } mbr_hubbard_desc;
 
 /* H = -sum_b t_b sum_s (c+_{i s} c_{j s} + h.c.) + sum_i U_i n_{i up} n_{i dn}
  *     + sum_{i s} eps_i n_{i s}, restricted to the listed (N_up, N_dn) sectors.
  * Vectors are the concatenation of the sectors in list order; within a sector
- * the index is rank_up * C(L, n_dn) + rank_dn (Eq. rankupdown). */
+ * the index is rank_up * C(L, n_dn) + rank_dn (Eq. rankupdown), which is also
+ * the position of the pattern (up half << L | down half) in the sector's
+ * ascending list.
+ * rank_kind selects how hop targets are ranked.  MBR_HV_RANK_HALVES (the
+ * default): only the half a hop changes is re-ranked, by staggered lookup on
+ * L-bit halves.  MBR_HV_RANK_TRIE: the plain trie method inside H·x (Sec. V.B
+ * compares it with staggered lookup): the library builds each sector's list
+ * and a packed trie over its full 2L-bit patterns (2L <= 32), reads every row's
+ * pattern from the list and ranks every hop target by a trie walk (a hop
+ * target of a spin sector is always a member, so no membership read).  Both
+ * kinds sum each row's terms in the same order, so their products are
+ * bitwise equal; the trie kind has one launch shape (set_config and autotune
+ * return EUNSUPPORTED). */
 mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void *stream);
 
 /* Total dimension and, if offsets != NULL, the n_sectors+1 sector offsets. */
@@ -417,11 +452,14 @@ mbr_status mbr_hubbard_apply(const mbr_hubbard *h, const void *d_x, void *d_y, v
 mbr_status mbr_hubbard_destroy(mbr_hubbard *h);
 
 /* Launch shape of the H·x kernel (extension: the paper has no GPU layout).
- * k: half-pattern chunk width of the staggered rank; G: 0 selects the
- * alpha_dn-stationary rows kernel (1024-lane workgroups, one per CU, down-hop
- * lists ranked once per launch shape) for every sector it supports (at most
- * 4095 spin-down configurations and 15 bonds) and the tile kernel with two
- * blocks for the rest; G in {1,2,4} selects the tile kernel for every sector,
+ * k: half-pattern chunk width of the staggered rank; G: -1 selects the flat
+ * kernel for every sector (256-lane workgroups, one row per lane at a time,
+ * both halves ranked on the fly, no staged x and no barrier between rows);
+ * 0 selects the alpha_dn-stationary rows kernel (1024-lane workgroups, one
+ * per CU, down-hop lists ranked once per launch shape) for every sector it
+ * supports (at most 4095 spin-down configurations and 15 bonds) and the tile
+ * kernel with two blocks for the rest; G in {1,2,4} selects the tile kernel
+ * for every sector,
  * holding G alpha_up blocks per workgroup (the down-hop ranks of a lane are
  * reused G times); block: threads per workgroup of the tile kernel (256 or
  * 512).  tuned_ms is the autotuner's best time for one product (0 when not
@@ -437,7 +475,7 @@ typedef struct {
 
 mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg);
 
-/* Set the launch shape (k in 1..L, G in {0,1,2,4}, block in {256,512}); EUNSUPPORTED
+/* Set the launch shape (k in 1..L, G in {-1,0,1,2,4}, block in {256,512}); EUNSUPPORTED
  * when the tiles would not fit the LDS.  Lanczos handles created before the
  * change reject further steps (EINVAL): create them afterwards. */
 mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream);
@@ -494,6 +532,20 @@ mbr_status mbr_lanczos_destroy(mbr_lanczos *lz);
  * Result to d_e0[b]. */
 mbr_status mbr_tridiag_lowest(const double *d_alpha, const double *d_beta, const int32_t *d_len,
                               int32_t ld, int32_t n_batch, double *d_e0, void *stream);
+
+/* ======================================================================== */
+/* Measurement                                                              */
+/* ======================================================================== */
+
+/* Gather probe (a measurement primitive for the rooflines of the gather-bound
+ * kernels, not a step of the method): for each j < n, i = d_idx[j] mod
+ * entries, then depth times i = d_table[i] mod entries (each read's address
+ * comes from the one before, as in a trie walk), and d_out[j] = i.  entries
+ * is a power of two up to 2^32 (EINVAL otherwise), depth in 1..64.  lds = 1
+ * stages the table in LDS first, for entries <= 16384 (EINVAL beyond).
+ * d_table holds `entries` uint32 values, d_idx and d_out n each. */
+mbr_status mbr_probe_gather(const uint32_t *d_table, uint64_t entries, const uint32_t *d_idx, uint64_t n,
+                            int32_t depth, int32_t lds, uint32_t *d_out, void *stream);
 
 #ifdef __cplusplus
 }

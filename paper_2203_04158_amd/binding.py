@@ -18,7 +18,9 @@ NOT_FOUND = 0xFFFFFFFF
 
 RANKER_STAGGERED, RANKER_SPIN, RANKER_TRIE, RANKER_LEARNED, RANKER_BISECT, RANKER_CNS, RANKER_SAMPLED = (
     1, 2, 3, 4, 5, 6, 7)
+RANKER_BITMAP_TRIE = 8
 F64, F32 = 0, 1
+RANK_HALVES, RANK_TRIE = 0, 1
 
 _lib = None
 
@@ -72,7 +74,7 @@ class HubbardDesc(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_bonds", C.c_int32), ("bonds", C.POINTER(Bond)),
                 ("eps", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
                 ("n_sectors", C.c_int32), ("sectors", C.POINTER(SpinSector)),
-                ("precision", C.c_int32), ("k", C.c_int32)]
+                ("precision", C.c_int32), ("k", C.c_int32), ("rank_kind", C.c_int32)]
 
 
 class HubbardCfg(C.Structure):
@@ -105,6 +107,9 @@ _SIGS = {
     "mbr_build_spin_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                           C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_build_trie": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_build_bitmap_trie": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "mbr_bitmap_trie_levels": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mbr_learned_train": (C.c_int32, [C.c_void_p, C.POINTER(LearnedOpts), C.c_void_p,
                                       C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_learned_max_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64),
@@ -149,6 +154,8 @@ _SIGS = {
     "mbr_lanczos_result": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_lanczos_coeffs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbr_lanczos_destroy": (C.c_int32, [C.c_void_p]),
+    "mbr_probe_gather": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p]),
     "mbr_tridiag_lowest": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]),
 }
@@ -166,11 +173,27 @@ def lib() -> C.CDLL:
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2203_04158_amd.build`")
         L = C.CDLL(LIB_PATH)
+        missing = []
         for name, (res, args) in _SIGS.items():
-            f = getattr(L, name)
+            try:
+                f = getattr(L, name)
+            except AttributeError:
+                missing.append(name)
+                continue
             f.restype, f.argtypes = res, args
+        if missing:
+            # a library older than this binding: calling these raises
+            for name in missing:
+                setattr(L, name, _missing_symbol(name))
         _lib = L
     return _lib
+
+
+def _missing_symbol(name: str):
+    def call(*_a, **_k):
+        raise RuntimeError(f"{LIB_PATH} does not export {name}: rebuild it with "
+                           "`python -m paper_2203_04158_amd.build`")
+    return call
 
 
 def _check(fn: str, st: int) -> None:
@@ -349,6 +372,22 @@ def build_trie(sector: Sector, k: int, stream=None) -> Ranker:
     h = C.c_void_p()
     _check("mbr_build_trie", lib().mbr_build_trie(sector.handle, k, C.byref(h), _stream(stream)))
     return Ranker(h, keep=(sector,))
+
+
+def build_bitmap_trie(sector: Sector, k: int, stream=None) -> Ranker:
+    h = C.c_void_p()
+    _check("mbr_build_bitmap_trie", lib().mbr_build_bitmap_trie(sector.handle, k, C.byref(h), _stream(stream)))
+    return Ranker(h, keep=(sector,))
+
+
+def bitmap_trie_levels(ranker: Ranker):
+    """(records per level, bytes per record, number of top levels staged in LDS)."""
+    rec = np.zeros(64, dtype=np.uint64)
+    rb = np.zeros(64, dtype=np.uint32)
+    lv, ld = C.c_int32(), C.c_int32()
+    _check("mbr_bitmap_trie_levels", lib().mbr_bitmap_trie_levels(
+        ranker.handle, C.c_void_p(rec.ctypes.data), C.c_void_p(rb.ctypes.data), 64, C.byref(lv), C.byref(ld)))
+    return [int(v) for v in rec[: lv.value]], [int(v) for v in rb[: lv.value]], int(ld.value)
 
 
 def build_bisect_ranker(sector: Sector) -> Ranker:
@@ -559,14 +598,15 @@ class Hubbard:
 
 
 def hubbard_create(L: int, bonds, sectors, U=None, eps=None, precision: int = F64, k: int = 0,
-                   stream=None) -> Hubbard:
-    """bonds: [(i, j, t)]; sectors: [(n_up, n_dn)]; U, eps: per-site lists or None."""
+                   rank_kind: int = 0, stream=None) -> Hubbard:
+    """bonds: [(i, j, t)]; sectors: [(n_up, n_dn)]; U, eps: per-site lists or None;
+    rank_kind: RANK_HALVES (staggered halves) or RANK_TRIE (trie over full patterns)."""
     b = (Bond * max(1, len(bonds)))(*[Bond(int(i), int(j), float(t)) for i, j, t in bonds])
     s = (SpinSector * len(sectors))(*[SpinSector(int(u), int(d)) for u, d in sectors])
     Uv = (C.c_double * L)(*[float(u) for u in U]) if U is not None else None
     ev = (C.c_double * L)(*[float(e) for e in eps]) if eps is not None else None
     d = HubbardDesc(L=L, n_bonds=len(bonds), bonds=b, eps=ev, U=Uv, n_sectors=len(sectors),
-                    sectors=s, precision=precision, k=k)
+                    sectors=s, precision=precision, k=k, rank_kind=rank_kind)
     h = C.c_void_p()
     _check("mbr_hubbard_create", lib().mbr_hubbard_create(C.byref(d), C.byref(h), _stream(stream)))
     return Hubbard(h, precision, len(sectors))
@@ -659,6 +699,19 @@ def tridiag_lowest(alpha, beta, lengths, ld: int, out=None, stream=None):
                                                           _dvec(beta, 8, nb * ld, "beta"),
                                                           _dvec(lengths, 4, nb, "lengths"), ld, nb,
                                                           _dvec(out, 8, nb, "out"), _stream(stream)))
+    return out
+
+
+def probe_gather(table, idx, depth: int = 1, lds: bool = False, out=None, stream=None):
+    """Gather probe: out[j] = the index reached after `depth` chained reads
+    i <- table[i] mod len(table), starting from idx[j] mod len(table)."""
+    torch = _torch()
+    n = idx.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check("mbr_probe_gather", lib().mbr_probe_gather(_dvec(table, 4, table.numel(), "table"), table.numel(),
+                                                      _dvec(idx, 4, n, "idx"), n, depth, int(lds),
+                                                      _dvec(out, 4, n, "out"), _stream(stream)))
     return out
 
 

@@ -152,6 +152,20 @@ struct TrieLevels {
     mbr::DevBuf table;         // uint32 entries of all levels
 };
 
+// Bitmap trie (bitmap_trie.hip): records {base, bitmap} per node, levels
+// from the most significant chunk.
+struct BitmapTrie {
+    int32_t M = 0, H = 0;
+    int32_t w[32] = {0};        // chunk widths, most significant first
+    int32_t shift[32] = {0};    // bit offset of chunk l in the pattern
+    uint32_t rw[32] = {0};      // record words of level l
+    uint64_t off[33] = {0};     // first word of level l (64-byte aligned)
+    uint64_t nodes[32] = {0};   // records of level l
+    int32_t lds_levels = 0;     // levels 0..lds_levels-1 are staged in LDS
+    uint64_t lds_words = 0;
+    mbr::DevBuf table;
+};
+
 struct LearnedModel;
 
 struct mbr_ranker {
@@ -166,6 +180,7 @@ struct mbr_ranker {
     mbr::DevBuf unrank_tab;    // spin: half lists (uint16) or binomial table for unranking
     bool unrank_lists = false; // spin: unrank_tab holds the half lists
     TrieLevels *trie = nullptr;
+    BitmapTrie *btrie = nullptr;
     LearnedModel *learned = nullptr;
     const mbr_sector *sector = nullptr;
     const mbr_ranker *fallback = nullptr;
@@ -190,6 +205,9 @@ mbr_status spin_unrank_build(mbr_ranker *r, hipStream_t s);
 mbr_status rank_cns_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
                            hipStream_t s);
 void trie_free(TrieLevels *t);
+void bitmap_trie_free(BitmapTrie *t);
+mbr_status rank_bitmap_trie_launch(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *out,
+                                   hipStream_t s);
 uint64_t trie_bytes(const TrieLevels *t);
 int32_t trie_levels(const TrieLevels *t);
 void learned_free(LearnedModel *m);

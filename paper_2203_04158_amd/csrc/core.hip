@@ -77,6 +77,7 @@ int device_cu_count() {
 
 mbr_ranker::~mbr_ranker() {
     if (trie) trie_free(trie);
+    if (btrie) bitmap_trie_free(btrie);
     if (learned) learned_free(learned);
 }
 
@@ -122,6 +123,10 @@ mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info) {
             o.bytes = learned_bytes(r->learned);
             o.levels = 0;
             break;
+        case MBR_RANKER_BITMAP_TRIE:
+            o.bytes = r->btrie ? r->btrie->table.bytes : 0;
+            o.levels = r->btrie ? r->btrie->H : 0;
+            break;
         case MBR_RANKER_SAMPLED:
             o.bytes = learned_bytes(r->learned);
             o.levels = learned_levels(r->learned);
@@ -151,6 +156,7 @@ mbr_status mbr_rank_batch(const mbr_ranker *r, const void *d_q, uint64_t n, uint
         case MBR_RANKER_STAGGERED: return rank_staggered_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_SPIN: return rank_spin_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_TRIE: return rank_trie_launch(r, d_q, n, d_rank, s);
+        case MBR_RANKER_BITMAP_TRIE: return rank_bitmap_trie_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_LEARNED:
         case MBR_RANKER_SAMPLED: return rank_learned_launch(r, d_q, n, d_rank, s);
         case MBR_RANKER_BISECT: return rank_bisect_launch(r, d_q, n, d_rank, s);

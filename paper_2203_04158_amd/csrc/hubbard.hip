@@ -29,6 +29,7 @@
 #include <sstream>
 
 #include "hubbard.hpp"
+#include "rank_device.hpp"
 
 using namespace mbr;
 
@@ -36,8 +37,28 @@ namespace {
 constexpr int kXcd = 8;
 }
 
+// Trie of one sector for the trie-ranked product: levels of a packed trie
+// over the sector's full 2L-bit patterns (level-major layout of trie.hip).
+struct HvTrieDesc {
+    const uint32_t *tab;     // all levels
+    const uint32_t *states;  // the sector's ascending list
+    uint32_t H, lds_levels, lds_entries, pad;
+    uint32_t wmask[8];
+    int32_t shift[8];
+    uint64_t off[9];
+};
+
 struct mbr_hubbard {
     int32_t L = 0, nb = 0, precision = MBR_F64;
+    int32_t rank_kind = MBR_HV_RANK_HALVES;
+    std::vector<mbr_sector *> tsecs;    // trie-ranked product: each sector's list and trie
+    std::vector<mbr_ranker *> ttries;
+    DevBuf d_trie;                      // HvTrieDesc per sector
+    uint32_t trie_lds = 0;              // LDS entries the largest staged top levels need
+    ~mbr_hubbard() {
+        for (auto *r : ttries) mbr_ranker_destroy(r);
+        for (auto *s : tsecs) mbr_sector_destroy(s);
+    }
     std::vector<mbr_bond> bonds;
     std::vector<double> eps, U;
     std::vector<mbr_spin_sector> secs;
@@ -52,6 +73,9 @@ struct mbr_hubbard {
     std::vector<HvTile> tiles_binned;   // tile-kernel tiles, XCD ranges, natural order inside
     uint32_t xoff[kXcd + 1] = {0};
     std::vector<HvTile> rows_tiles;     // alpha_dn-stationary kernel tiles, natural order
+    std::vector<HvTile> flat_tiles;     // flat kernel tiles, natural order
+    DevBuf d_flat_tiles;
+    uint32_t flat_xoff[kXcd + 1] = {0};
     DevBuf d_rdesc, d_rdesc_slot;       // their descriptors, and descriptors in slot order
     uint32_t rows_xoff[kXcd + 1] = {0};
     uint32_t rows_xcap = 0, rows_gmax = 1;
@@ -107,6 +131,7 @@ struct HvArgs {
     const uint16_t *rtab;
     uint32_t rtab_entries;
     int32_t nb, k, nch;
+    int32_t Lsites;
     int32_t rowoff[kMaxSites];
     uint32_t bmask[kMaxBonds];
     uint32_t bbetw[kMaxBonds];
@@ -1012,6 +1037,268 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
     }
 }
 
+// ------------------------------------------------------------------------
+// Flat kernel.  Every row is independent work for one lane: no staged x, no
+// down-hop lists, no barrier between rows, so a CU holds as many waves as its
+// registers allow and their gathers overlap.  A 256-lane workgroup takes one
+// tile (a few alpha_up blocks of one sector, about kFlatRows rows); lane t
+// handles rows t, t + 256, ... of the tile, splitting each into (alpha_up,
+// alpha_dn) with the sector's reciprocal multiplier.  Both halves' hops are
+// ranked on the LDS table (Fig. fastrank) for every bond, branch-free: a bond
+// that does not hop gets coefficient 0 and the row's own x.  Down-hop
+// sources lie in the row's own alpha_up block (3.7 KB in fp32 for the
+// 12-site impurity model, L1/L2 resident), up-hop sources in the same
+// alpha_dn column of other blocks (contiguous across lanes).  The terms are
+// summed in the order of the rows kernel (down-hops in bond order, the
+// diagonal, up-hops in bond order) with the same fused operations, so both
+// give bitwise identical products.  Tiles are binned by XCD like the other
+// kernels, so a sector's x is gathered through one L2.
+// ------------------------------------------------------------------------
+constexpr int kFlatBlock = 256;
+constexpr uint32_t kFlatRows = 1024;  // rows per tile (whole alpha_up blocks; at least one)
+
+template <class T, int NCH, bool LZ>
+__global__ void __launch_bounds__(kFlatBlock) hv_flat_kernel(HvArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *rt = reinterpret_cast<uint16_t *>(smem);
+    double *red = reinterpret_cast<double *>(smem + ((a.rtab_entries * 2 + 15) & ~15u));
+    for (uint32_t i = threadIdx.x; i < a.rtab_entries; i += blockDim.x) rt[i] = a.rtab[i];
+
+    uint32_t ti;
+    if (a.binned) {
+        const uint32_t xcd = blockIdx.x % kXcd;
+        ti = a.xoff[xcd] + blockIdx.x / kXcd;
+        if (ti >= a.xoff[xcd + 1]) return;  // whole workgroup: no barrier is skipped by part of it
+    } else {
+        ti = blockIdx.x;
+        if (ti >= a.n_tiles) return;
+    }
+    const T *x = static_cast<const T *>(a.x);
+    T *out = static_cast<T *>(a.out);
+    const T *p = static_cast<const T *>(a.ep.p);
+    if (a.ep.basis_j) {
+        const int64_t j = *a.ep.basis_j;
+        x += (uint64_t)j * a.ep.basis_stride;
+        p = j > 0 ? x - a.ep.basis_stride : x;
+    }
+    const HvTile tl = a.tiles[ti];
+    const HvSector sc = a.secs[tl.sector];
+    __syncthreads();  // rank table in LDS
+    const bool active = !a.ep.active || a.ep.active[tl.sector];
+    double dot = 0.0;
+    if (active) {
+        const uint32_t cdn = sc.cdn;
+        const uint32_t rows = tl.nblk * cdn;
+        const T *xs = x + sc.off;
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * cdn;
+        const int nb = a.nb;
+        const bool has_p = LZ && a.ep.c2 != nullptr;
+        const T c1 = LZ ? (T)a.ep.c1[tl.sector] : (T)1;
+        const T c2 = has_p ? (T)a.ep.c2[tl.sector] : (T)0;
+        const T tu = (T)a.bamp[0];
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            uint32_t g = __umulhi(e, sc.magic);
+            uint32_t rd = e - g * cdn;
+            if (rd >= cdn) {
+                rd -= cdn;
+                ++g;
+            }
+            const uint32_t ru = tl.rup0 + g;
+            const uint32_t au = a.hs_states[sc.hs_up + ru], ad = a.hs_states[sc.hs_dn + rd];
+            const T eu = (T)a.hs_energy[sc.hs_up + ru], ed = (T)a.hs_energy[sc.hs_dn + rd];
+            const uint64_t ubase = (uint64_t)ru * cdn;  // row of this alpha_up block, in the sector
+            const T xv = xs[ubase + rd];
+            T pv = 0;
+            if constexpr (LZ) {
+                if (has_p) pv = p[base + e];
+            }
+            T acc = 0;
+#pragma unroll 4
+            for (int b = 0; b < nb; ++b) {
+                const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+                const bool hop = ((ad >> bi) ^ (ad >> bj)) & 1;
+                uint32_t rr = rank_half<NCH>(ad ^ a.bmask[b], rt, a);
+                rr = hop ? rr : rd;
+                const T mag = a.t_uniform ? (T)1 : (T)a.bamp[b];
+                T c = (__popc(ad & a.bbetw[b]) & 1) ? mag : -mag;
+                c = hop ? c : (T)0;
+                acc = fma_t(c, xs[ubase + rr], acc);
+            }
+            const T dg = eu + ed + u_energy<T>(au & ad, a);
+            T v = fma_t(dg, xv, a.t_uniform ? tu * acc : acc);
+#pragma unroll 4
+            for (int b = 0; b < nb; ++b) {
+                const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+                const bool hop = ((au >> bi) ^ (au >> bj)) & 1;
+                uint32_t rr = rank_half<NCH>(au ^ a.bmask[b], rt, a);
+                rr = hop ? rr : ru;
+                T c = (__popc(au & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
+                c = hop ? c : (T)0;
+                v = fma_t(c, xs[(uint64_t)rr * cdn + rd], v);
+            }
+            if constexpr (LZ) {
+                const T uu = lz_out(v, c1, c2, pv, has_p);
+                out[base + e] = uu;
+                dot = __builtin_fma((double)xv, (double)uu, dot);
+            } else {
+                out[base + e] = v;
+            }
+        }
+    }
+    if (a.ep.partial) {
+        double v = dot;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kFlatBlock / 64; ++w) s += red[w];
+            a.ep.partial[tl.slot] = active ? s : 0.0;
+        }
+    }
+}
+
+// Trie-ranked product (the plain trie method of Sec. IV inside H·x, which
+// Sec. V.B compares with staggered lookup): the flat kernel's tiles and sums,
+// but the row's pattern is read from the sector's list and every hop
+// target's full 2L-bit pattern is ranked by a walk through the sector's
+// packed trie, its top levels staged in LDS.  Every hop target of a spin
+// sector is a member, so the walk's value is its rank (no membership read).
+// Terms are summed in the order of the other kernels, so the products are
+// bitwise equal to theirs.
+template <class T, bool LZ>
+__global__ void __launch_bounds__(kFlatBlock) hv_trie_kernel(HvArgs a, const HvTrieDesc *__restrict__ tries,
+                                                             uint32_t lds_cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *top = reinterpret_cast<uint32_t *>(smem);
+    double *red = reinterpret_cast<double *>(smem + (size_t)lds_cap * 4);
+    uint32_t ti;
+    if (a.binned) {
+        const uint32_t xcd = blockIdx.x % kXcd;
+        ti = a.xoff[xcd] + blockIdx.x / kXcd;
+        if (ti >= a.xoff[xcd + 1]) return;
+    } else {
+        ti = blockIdx.x;
+        if (ti >= a.n_tiles) return;
+    }
+    const HvTile tl = a.tiles[ti];
+    const HvSector sc = a.secs[tl.sector];
+    const HvTrieDesc td = tries[tl.sector];
+    stage_to_lds(top, td.tab, (uint64_t)td.lds_entries * 4);
+    const T *x = static_cast<const T *>(a.x);
+    T *out = static_cast<T *>(a.out);
+    const T *p = static_cast<const T *>(a.ep.p);
+    if (a.ep.basis_j) {
+        const int64_t j = *a.ep.basis_j;
+        x += (uint64_t)j * a.ep.basis_stride;
+        p = j > 0 ? x - a.ep.basis_stride : x;
+    }
+    __syncthreads();  // staged levels in LDS
+    const bool active = !a.ep.active || a.ep.active[tl.sector];
+    double dot = 0.0;
+    if (active) {
+        const int L = a.Lsites;
+        const uint32_t lo_mask = (1u << L) - 1;
+        const uint32_t cdn = sc.cdn;
+        const uint32_t rows = tl.nblk * cdn;
+        const T *xs = x + sc.off;
+        const uint64_t base = sc.off + (uint64_t)tl.rup0 * cdn;
+        const uint32_t lbase = tl.rup0 * cdn;  // first row of the tile within the sector
+        const int nb = a.nb;
+        const bool has_p = LZ && a.ep.c2 != nullptr;
+        const T c1 = LZ ? (T)a.ep.c1[tl.sector] : (T)1;
+        const T c2 = has_p ? (T)a.ep.c2[tl.sector] : (T)0;
+        const T tu = (T)a.bamp[0];
+        auto walk = [&](uint32_t alpha) {
+            uint32_t node = 0;
+            uint32_t l = 0;
+            for (; l < td.lds_levels; ++l) node = top[td.off[l] + node + ((alpha >> td.shift[l]) & td.wmask[l])];
+            for (; l < td.H; ++l) node = td.tab[td.off[l] + node + ((alpha >> td.shift[l]) & td.wmask[l])];
+            return node;
+        };
+        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
+            uint32_t g = __umulhi(e, sc.magic);
+            uint32_t rd = e - g * cdn;
+            if (rd >= cdn) {
+                rd -= cdn;
+                ++g;
+            }
+            const uint32_t ru = tl.rup0 + g;
+            const uint32_t own = lbase + e;
+            const uint32_t alpha = td.states[own];
+            const uint32_t ad = alpha & lo_mask, au = alpha >> L;
+            const T eu = (T)a.hs_energy[sc.hs_up + ru], ed = (T)a.hs_energy[sc.hs_dn + rd];
+            const T xv = xs[own];
+            T pv = 0;
+            if constexpr (LZ) {
+                if (has_p) pv = p[base + e];
+            }
+            T acc = 0;
+            for (int b = 0; b < nb; ++b) {
+                const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+                const bool hop = ((ad >> bi) ^ (ad >> bj)) & 1;
+                const uint32_t rr = hop ? walk(alpha ^ a.bmask[b]) : own;
+                const T mag = a.t_uniform ? (T)1 : (T)a.bamp[b];
+                T c = (__popc(ad & a.bbetw[b]) & 1) ? mag : -mag;
+                c = hop ? c : (T)0;
+                acc = fma_t(c, xs[rr], acc);
+            }
+            const T dg = eu + ed + u_energy<T>(au & ad, a);
+            T v = fma_t(dg, xv, a.t_uniform ? tu * acc : acc);
+            for (int b = 0; b < nb; ++b) {
+                const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+                const bool hop = ((au >> bi) ^ (au >> bj)) & 1;
+                const uint32_t rr = hop ? walk(alpha ^ (a.bmask[b] << L)) : own;
+                T c = (__popc(au & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
+                c = hop ? c : (T)0;
+                v = fma_t(c, xs[rr], v);
+            }
+            if constexpr (LZ) {
+                const T uu = lz_out(v, c1, c2, pv, has_p);
+                out[base + e] = uu;
+                dot = __builtin_fma((double)xv, (double)uu, dot);
+            } else {
+                out[base + e] = v;
+            }
+        }
+    }
+    if (a.ep.partial) {
+        double v = dot;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kFlatBlock / 64; ++w) s += red[w];
+            a.ep.partial[tl.slot] = active ? s : 0.0;
+        }
+    }
+}
+
+template <class T, bool LZ>
+mbr_status launch_trie_hv(const mbr_hubbard *h, const HvArgs &a, unsigned grid, hipStream_t s) {
+    const size_t lds = (size_t)h->trie_lds * 4 + 4 * sizeof(double);
+    auto kern = hv_trie_kernel<T, LZ>;
+    if (lds > 64 * 1024)
+        MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (grid) kern<<<grid, kFlatBlock, lds, s>>>(a, h->d_trie.as<HvTrieDesc>(), h->trie_lds);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
+template <class T, int NCH, bool LZ>
+mbr_status launch_flat(const HvArgs &a, unsigned grid, hipStream_t s) {
+    const size_t lds = ((a.rtab_entries * 2 + 15) & ~(size_t)15) + 4 * sizeof(double);
+    auto kern = hv_flat_kernel<T, NCH, LZ>;
+    if (lds > 64 * 1024)
+        MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (grid) kern<<<grid, kFlatBlock, lds, s>>>(a);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
 size_t lds_bytes_for(const mbr_hubbard *h, size_t tsz) {
     auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
     size_t o = r16(((size_t)h->tab.nrows << h->tab.k) * 2);
@@ -1047,6 +1334,7 @@ void fill_args(const mbr_hubbard *h, HvArgs &a, const void *x, void *out, const 
     a.rtab = h->tab.table.as<uint16_t>();
     a.rtab_entries = (uint32_t)((uint64_t)h->tab.nrows << h->tab.k);
     a.nb = h->nb;
+    a.Lsites = h->L;
     a.k = h->tab.k;
     a.nch = h->tab.nch;
     for (int c = 0; c < kMaxSites; ++c) a.rowoff[c] = c < h->tab.nch ? h->tab.rowoff[c] : 0;
@@ -1075,25 +1363,35 @@ void fill_args(const mbr_hubbard *h, HvArgs &a, const void *x, void *out, const 
     a.ep = ep;
 }
 
+// The rows kernel runs as many 1024-lane workgroups per CU as its registers
+// and LDS allow, at most two: a CU then has a second sweep of tiles whose
+// gathers are in flight while the first one waits (short spin-down blocks
+// leave one tile's gathers too few to cover the latency).  cap: the number of
+// tiles of a per-sector launch, 0 for a whole product.
 template <class T, bool LZ, int R>
-mbr_status launch_rows_r(const mbr_hubbard *h, const HvArgs &a, unsigned grid, hipStream_t s) {
+mbr_status launch_rows_r(const mbr_hubbard *h, const HvArgs &a, unsigned cap, hipStream_t s) {
     auto kern = h->t_uniform ? hv_rows_kernel<T, LZ, R, true> : hv_rows_kernel<T, LZ, R, false>;
     const size_t lds = rows_lds_layout(a.rtab_entries, a.xcap, a.rgmax, sizeof(T)).total;
     if (lds > 64 * 1024)
         MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kRowsBlock, lds) != hipSuccess) per_cu = 1;
+    per_cu = std::max(1, std::min(per_cu, 2));
+    unsigned grid = (unsigned)h->rows_grid * (unsigned)per_cu;
+    if (cap) grid = std::min(grid, cap);
     kern<<<grid, kRowsBlock, lds, s>>>(a);
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }
 
 template <class T, bool LZ>
-mbr_status launch_rows(const mbr_hubbard *h, const HvArgs &a, unsigned grid, int R, hipStream_t s) {
+mbr_status launch_rows(const mbr_hubbard *h, const HvArgs &a, unsigned cap, int R, hipStream_t s) {
     switch (R) {
-        case 1: return launch_rows_r<T, LZ, 1>(h, a, grid, s);
-        case 2: return launch_rows_r<T, LZ, 2>(h, a, grid, s);
-        case 3: return launch_rows_r<T, LZ, 3>(h, a, grid, s);
-        default: return launch_rows_r<T, LZ, 4>(h, a, grid, s);
+        case 1: return launch_rows_r<T, LZ, 1>(h, a, cap, s);
+        case 2: return launch_rows_r<T, LZ, 2>(h, a, cap, s);
+        case 3: return launch_rows_r<T, LZ, 3>(h, a, cap, s);
+        default: return launch_rows_r<T, LZ, 4>(h, a, cap, s);
     }
 }
 
@@ -1108,19 +1406,44 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
         a.n_tiles = ep.n_tiles;
         a.binned = 0;
         if (ep.n_tiles == 0) return MBR_OK;
+        if (h->rank_kind == MBR_HV_RANK_TRIE) {
+            if (ep.c1) return launch_trie_hv<T, true>(h, a, ep.n_tiles, s);
+            return launch_trie_hv<T, false>(h, a, ep.n_tiles, s);
+        }
+        if (!h->flat_tiles.empty()) {
+            if (ep.c1) return launch_flat<T, NCH, true>(a, ep.n_tiles, s);
+            return launch_flat<T, NCH, false>(a, ep.n_tiles, s);
+        }
         if (h->hsec[ep.sector].rows) {
             // the sector's tiles are the slot range starting at its first slot
             a.rdesc = h->d_rdesc_slot.as<RowsTileDesc>() + h->hsec[ep.sector].slot0;
             a.xcap = h->rows_xcap;
-            const unsigned grid = (unsigned)std::min<uint64_t>(ep.n_tiles, (uint64_t)h->rows_grid);
-            if (ep.c1) return launch_rows<T, true>(h, a, grid, h->hsec[ep.sector].R, s);
-            return launch_rows<T, false>(h, a, grid, h->hsec[ep.sector].R, s);
+            if (ep.c1) return launch_rows<T, true>(h, a, ep.n_tiles, h->hsec[ep.sector].R, s);
+            return launch_rows<T, false>(h, a, ep.n_tiles, h->hsec[ep.sector].R, s);
         }
         a.xcap = h->xcap;
         const size_t lds = lds_bytes_for(h, sizeof(T));
         const unsigned grid = (unsigned)std::min<uint64_t>(a.n_tiles, (uint64_t)h->grid);
         if (ep.c1) return launch_g<T, NCH, true>(h, a, grid, lds, s);
         return launch_g<T, NCH, false>(h, a, grid, lds, s);
+    }
+    if (!h->flat_tiles.empty()) {
+        a.tiles = h->d_flat_tiles.as<HvTile>();
+        a.n_tiles = (uint32_t)h->flat_tiles.size();
+        a.binned = 1;
+        uint32_t most = 0;
+        for (int i = 0; i < kXcd; ++i) {
+            a.xoff[i] = h->flat_xoff[i];
+            most = std::max(most, h->flat_xoff[i + 1] - h->flat_xoff[i]);
+        }
+        a.xoff[kXcd] = h->flat_xoff[kXcd];
+        const unsigned grid = most * kXcd;
+        if (h->rank_kind == MBR_HV_RANK_TRIE) {
+            if (ep.c1) return launch_trie_hv<T, true>(h, a, grid, s);
+            return launch_trie_hv<T, false>(h, a, grid, s);
+        }
+        if (ep.c1) return launch_flat<T, NCH, true>(a, grid, s);
+        return launch_flat<T, NCH, false>(a, grid, s);
     }
     if (!h->rows_tiles.empty()) {
         HvArgs ar = a;
@@ -1129,8 +1452,8 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
         ar.binned = 1;
         for (int i = 0; i <= kXcd; ++i) ar.xoff[i] = h->rows_xoff[i];
         ar.xcap = h->rows_xcap;
-        if (ep.c1) MBR_TRY((launch_rows<T, true>(h, ar, h->rows_grid, h->rows_R, s)));
-        else MBR_TRY((launch_rows<T, false>(h, ar, h->rows_grid, h->rows_R, s)));
+        if (ep.c1) MBR_TRY((launch_rows<T, true>(h, ar, 0, h->rows_R, s)));
+        else MBR_TRY((launch_rows<T, false>(h, ar, 0, h->rows_R, s)));
     }
     if (!h->tiles_binned.empty()) {
         a.tiles = h->d_tiles.as<HvTile>();
@@ -1209,7 +1532,8 @@ mbr_status build_lists(mbr_hubbard *h, uint32_t lrows, hipStream_t s) {
 mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     const int L = h->L;
     if (k < 1 || k > L || k > 16) MBR_FAIL(MBR_EINVAL, "k=%d outside 1..L", k);
-    if (G != 0 && G != 1 && G != 2 && G != 4) MBR_FAIL(MBR_EINVAL, "G=%d not in {0,1,2,4}", G);
+    if (G != -1 && G != 0 && G != 1 && G != 2 && G != 4) MBR_FAIL(MBR_EINVAL, "G=%d not in {-1,0,1,2,4}", G);
+    const bool flat = G == -1;
     if (block != 256 && block != 512) MBR_FAIL(MBR_EINVAL, "block=%d not in {256,512}", block);
     StagTable tab;
     MBR_TRY(stag_build(tab, L, k, L, 2, s));
@@ -1220,7 +1544,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     const int Gt = G == 0 ? 2 : G;  // tile-kernel blocks for sectors the rows kernel does not take
     const size_t xbudget = (Gt == 4 ? 112 : 56) * 1024;
     std::vector<HvSector> hsec;
-    std::vector<HvTile> tiles, rows_tiles, other_tiles;
+    std::vector<HvTile> tiles, rows_tiles, other_tiles, flat_tiles;
     uint64_t off = 0;
     uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0, rows_gmax = 1, lrows = 0;
     std::vector<uint32_t> lists_ndn, lists_rows;
@@ -1234,8 +1558,13 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
         sc.hs_up = h->hs_off[h->secs[si].n_up];
         sc.hs_dn = h->hs_off[h->secs[si].n_dn];
         sc.rows = (G == 0 && sc.cdn + 1 <= kRowsMaxX && h->nb <= kRowsNB - 1) ? 1 : 0;
+        sc.magic = sc.cdn == 1 ? 0xFFFFFFFFu : (uint32_t)((1ull << 32) / sc.cdn);
         uint32_t nblk;
-        if (sc.rows) {
+        if (flat) {
+            sc.wide = 0;
+            sc.x_lds = 0;
+            nblk = std::max<uint32_t>(1, kFlatRows / sc.cdn);
+        } else if (sc.rows) {
             sc.wide = 1;
             sc.x_lds = 1;
             sc.gp = sc.cdn <= (uint32_t)kRowsBlock / 2 ? std::min<uint32_t>(kRowsMaxG, kRowsBlock / sc.cdn) : 1;
@@ -1264,7 +1593,9 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             t.rup0 = r;
             t.nblk = std::min(nblk, sc.cup - r);
             t.slot = slot++;
-            if (sc.rows) {
+            if (flat) {
+                flat_tiles.push_back(t);
+            } else if (sc.rows) {
                 rows_xcap = std::max(rows_xcap, t.nblk * (sc.cdn + 1));
                 rows_tiles.push_back(t);
             } else {
@@ -1297,6 +1628,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     rows_grid -= rows_grid % kXcd;
     if (rows_grid < kXcd) rows_grid = kXcd;
     const std::vector<uint32_t> rr = balanced_ranges(rows_tiles, hsec, kXcd);
+    const std::vector<uint32_t> fr = balanced_ranges(flat_tiles, hsec, kXcd);
     const size_t rows_lds = rows_lds_layout((uint32_t)((uint64_t)tab.nrows << k), rows_xcap, rows_gmax, tsz).total;
     if (!rows_tiles.empty() && rows_lds > kLdsMax) MBR_FAIL(MBR_EUNSUPPORTED, "rows kernel needs %zu bytes of LDS", rows_lds);
     bool t_uniform = true;
@@ -1312,6 +1644,9 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     h->tiles_by_slot = tiles;
     h->tiles_binned = other_tiles;
     h->rows_tiles = rows_tiles;
+    h->flat_tiles = flat_tiles;
+    for (int b = 0; b <= kXcd; ++b) h->flat_xoff[b] = fr[b];
+    MBR_TRY(upload(h->d_flat_tiles, flat_tiles.data(), flat_tiles.size() * sizeof(HvTile), s));
     for (int b = 0; b <= kXcd; ++b) h->xoff[b] = xr[b];
     h->xcap = xcap;
     h->upcap = upcap;
@@ -1350,6 +1685,9 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     for (int b = 0; b <= kXcd; ++b) h->rows_xoff[b] = rr[b];
     MBR_TRY(upload(h->d_secs, h->hsec.data(), h->hsec.size() * sizeof(HvSector), s));
     h->lds_bytes = std::max(other_tiles.empty() ? 0 : lds_bytes_for(h, tsz), rows_tiles.empty() ? 0 : rows_lds);
+    if (!flat_tiles.empty())
+        h->lds_bytes = std::max<size_t>(h->lds_bytes, ((((size_t)h->tab.nrows << h->tab.k) * 2 + 15) & ~(size_t)15) +
+                                                          4 * sizeof(double));
     if (!other_tiles.empty() && lds_bytes_for(h, tsz) > kLdsMax)
         MBR_FAIL(MBR_EUNSUPPORTED, "tile needs %zu bytes of LDS", lds_bytes_for(h, tsz));
     const size_t tl = other_tiles.empty() ? 1 : lds_bytes_for(h, tsz);
@@ -1401,6 +1739,12 @@ mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void
     if (d->n_sectors < 1 || d->n_sectors > 1024 || !d->sectors) MBR_FAIL(MBR_EINVAL, "n_sectors=%d", d->n_sectors);
     if (d->precision != MBR_F64 && d->precision != MBR_F32) MBR_FAIL(MBR_EINVAL, "precision=%d", d->precision);
     if (d->k < 0 || d->k > 16) MBR_FAIL(MBR_EINVAL, "k=%d outside 0..16", d->k);
+    if (d->rank_kind != MBR_HV_RANK_HALVES && d->rank_kind != MBR_HV_RANK_TRIE)
+        MBR_FAIL(MBR_EINVAL, "rank_kind=%d", d->rank_kind);
+    if (d->rank_kind == MBR_HV_RANK_TRIE && 2 * L > 32)
+        MBR_FAIL(MBR_EUNSUPPORTED, "trie ranks need 2L <= 32 (L=%d)", L);
+    if (d->rank_kind == MBR_HV_RANK_TRIE && d->k != 0 && d->k < 4)
+        MBR_FAIL(MBR_EINVAL, "trie chunk width k=%d below 4", d->k);
     for (int b = 0; b < d->n_bonds; ++b) {
         const mbr_bond &bd = d->bonds[b];
         if (bd.i < 0 || bd.i >= L || bd.j < 0 || bd.j >= L || bd.i == bd.j)
@@ -1437,6 +1781,46 @@ mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void
     h->hs_off[L + 1] = (uint32_t)hs.size();
     MBR_TRY(upload(h->d_hs_states, hs.data(), hs.size() * 2, s));
     MBR_TRY(upload(h->d_hs_energy, he.data(), he.size() * 8, s));
+    h->rank_kind = d->rank_kind;
+    if (h->rank_kind == MBR_HV_RANK_TRIE) {
+        // each sector's ascending list of 2L-bit patterns and a packed trie on
+        // it; chunk width k (0: four levels)
+        const int kt = d->k > 0 ? d->k : std::max(4, (2 * L + 3) / 4);
+        std::vector<HvTrieDesc> td;
+        const uint64_t lo = (1ull << L) - 1;
+        for (auto &sc : h->secs) {
+            const mbr_popc_cons cons[3] = {{(lo << L) | lo, sc.n_up + sc.n_dn, sc.n_up + sc.n_dn},
+                                           {lo, sc.n_dn, sc.n_dn},
+                                           {lo << L, sc.n_up, sc.n_up}};
+            mbr_sector *sec = nullptr;
+            MBR_TRY(mbr_sector_build(2 * L, 32, 3, cons, &sec, stream));
+            h->tsecs.push_back(sec);
+            mbr_ranker *tr = nullptr;
+            MBR_TRY(mbr_build_trie(sec, kt, &tr, stream));
+            h->ttries.push_back(tr);
+            const TrieLevels &t = *tr->trie;
+            if (t.H > 8) MBR_FAIL(MBR_EUNSUPPORTED, "trie of %d levels (at most 8)", t.H);
+            HvTrieDesc dd{};
+            dd.tab = t.table.as<uint32_t>();
+            dd.states = sec->states.as<uint32_t>();
+            dd.H = (uint32_t)t.H;
+            dd.lds_levels = (uint32_t)t.lds_levels;
+            dd.lds_entries = (uint32_t)t.lds_entries;
+            for (int l = 0; l < t.H; ++l) {
+                dd.wmask[l] = (uint32_t)((1ull << t.w[l]) - 1);
+                dd.shift[l] = t.shift[l];
+                dd.off[l] = t.off[l];
+            }
+            dd.off[t.H] = t.off[t.H];
+            h->trie_lds = std::max(h->trie_lds, dd.lds_entries);
+            td.push_back(dd);
+        }
+        h->trie_lds = (h->trie_lds + 3) & ~3u;  // the partial sums after it stay 16-byte aligned
+        MBR_TRY(upload(h->d_trie, td.data(), td.size() * sizeof(HvTrieDesc), s));
+        MBR_TRY(configure(h.get(), (L + 1) / 2, -1, 512, s));
+        *out = h.release();
+        return MBR_OK;
+    }
     // default launch shape: two lookups per half rank, two alpha_up blocks per tile
     const int k = d->k > 0 ? std::min(d->k, L) : (L + 1) / 2;
     mbr_status st = configure(h.get(), k, 0, 512, s);
@@ -1482,6 +1866,7 @@ mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg) {
 
 mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream) {
     if (!h) MBR_FAIL(MBR_EINVAL, "null handle");
+    if (h->rank_kind == MBR_HV_RANK_TRIE) MBR_FAIL(MBR_EUNSUPPORTED, "a trie-ranked product has one launch shape");
     const int ok = h->k, oG = h->G, ob = h->block;
     mbr_status st = configure(h, k, G, block, as_stream(stream));
     if (st != MBR_OK) {
@@ -1495,6 +1880,7 @@ mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t 
 mbr_status mbr_hubbard_autotune(mbr_hubbard *h, int32_t reps, void *stream) {
     if (!h) MBR_FAIL(MBR_EINVAL, "null handle");
     if (reps < 1 || reps > 1000) MBR_FAIL(MBR_EINVAL, "reps=%d", reps);
+    if (h->rank_kind == MBR_HV_RANK_TRIE) MBR_FAIL(MBR_EUNSUPPORTED, "a trie-ranked product has one launch shape");
     hipStream_t s = as_stream(stream);
     const std::string key = tune_key(h);
     const char *path = std::getenv("MBR_AUTOTUNE_CACHE");
@@ -1527,9 +1913,9 @@ mbr_status mbr_hubbard_autotune(mbr_hubbard *h, int32_t reps, void *stream) {
     int bk = h->k, bG = h->G, bb = h->block;
     double best = 1e30;
     for (int k : ks)
-        for (int G : {0, 1, 2, 4})
+        for (int G : {-1, 0, 1, 2, 4})
             for (int block : {256, 512}) {
-                if (G == 0 && block != 512) continue;  // the rows kernel has one block size
+                if (G <= 0 && block != 512) continue;  // the rows and flat kernels have one block size each
                 if (configure(h, k, G, block, s) != MBR_OK) continue;
                 HvEpilogue ep{};
                 if (hubbard_launch(h, bx.p, by.p, ep, s) != MBR_OK) continue;

@@ -70,8 +70,14 @@ struct MlpFrags {
     f32x4 b3;
 };
 
-// wb: bf16 weights in parameter order.
-__device__ __forceinline__ void load_frags(MlpFrags &f, const uint16_t *__restrict__ wb) {
+// bf16 bits of parameter i: stored as bf16, or rounded from fp32 as the
+// training kernels round them (mlp_round_kernel).
+__device__ __forceinline__ uint16_t wbits(const uint16_t *__restrict__ w, int i) { return w[i]; }
+__device__ __forceinline__ uint16_t wbits(const float *__restrict__ w, int i) { return f2bf(w[i]); }
+
+// wb: bf16 weights (or fp32 parameters) in parameter order.
+template <class W>
+__device__ __forceinline__ void load_frags(MlpFrags &f, const W *__restrict__ wb) {
     const int l = threadIdx.x & 63;
     const int row = l & 15, kg = (l >> 4) * 4;
 #pragma unroll
@@ -80,24 +86,24 @@ __device__ __forceinline__ void load_frags(MlpFrags &f, const uint16_t *__restri
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                f.w1[t][ks][j] = (short)wb[P_W1 + (16 * t + row) * kIn + 16 * ks + kg + j];
+                f.w1[t][ks][j] = (short)wbits(wb, P_W1 + (16 * t + row) * kIn + 16 * ks + kg + j);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                f.w2[t][ks][j] = (short)wb[P_W2 + (16 * t + row) * kH + 16 * ks + kg + j];
+                f.w2[t][ks][j] = (short)wbits(wb, P_W2 + (16 * t + row) * kH + 16 * ks + kg + j);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            f.b1[t][r] = bf2f(wb[P_B1 + 16 * t + kg + r]);
-            f.b2[t][r] = bf2f(wb[P_B2 + 16 * t + kg + r]);
+            f.b1[t][r] = bf2f(wbits(wb, P_B1 + 16 * t + kg + r));
+            f.b2[t][r] = bf2f(wbits(wb, P_B2 + 16 * t + kg + r));
         }
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            f.w3[ks][j] = row == 0 ? (short)wb[P_W3 + 16 * ks + kg + j] : (short)0;
-    const float b3 = bf2f(wb[P_B3]);
+            f.w3[ks][j] = row == 0 ? (short)wbits(wb, P_W3 + 16 * ks + kg + j) : (short)0;
+    const float b3 = bf2f(wbits(wb, P_B3));
     f.b3 = (f32x4){b3, b3, b3, b3};
 }
 
@@ -172,7 +178,8 @@ __device__ __forceinline__ int64_t predict_rank(float y, uint64_t n) {
 }
 
 // ---------------------------------------------------------------- inference
-__global__ void __launch_bounds__(256) mlp_forward_kernel(const uint16_t *__restrict__ wb,
+template <class W>
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const W *__restrict__ wb,
                                                           const uint32_t *__restrict__ q, int B,
                                                           float *__restrict__ out) {
     MlpFrags f;
@@ -933,13 +940,9 @@ mbr_status mbr_mlp_forward(const float *d_params, const uint32_t *d_q, int32_t B
     if (!d_params || !d_q || !d_pred) MBR_FAIL(MBR_EINVAL, "null pointer");
     if (B <= 0 || B % 64 != 0) MBR_FAIL(MBR_EINVAL, "B=%d must be a positive multiple of 64", B);
     hipStream_t s = as_stream(stream);
-    DevBuf wr, wb;
-    MBR_TRY(wr.alloc(kParams * 4));
-    MBR_TRY(wb.alloc(kParams * 2));
-    mlp_round_kernel<<<(kParams + 255) / 256, 256, 0, s>>>(d_params, wr.as<float>(), wb.as<uint16_t>());
-    mlp_forward_kernel<<<grid_for((uint64_t)B, 256, 4096), 256, 0, s>>>(wb.as<uint16_t>(), d_q, B, d_pred);
+    // each workgroup rounds the fp32 parameters to bf16 as it loads them
+    mlp_forward_kernel<float><<<grid_for((uint64_t)B, 256, 4096), 256, 0, s>>>(d_params, d_q, B, d_pred);
     MBR_HIP(hipGetLastError());
-    MBR_HIP(hipStreamSynchronize(s));  // scratch weights are released on return
     return MBR_OK;
 }
 

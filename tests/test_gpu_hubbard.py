@@ -298,8 +298,8 @@ def test_lanczos_anderson_169_sectors_mixed():
 def _shapes_equal(h, x, ks):
     ref = None
     for k in ks:
-        for G in (0, 1, 2, 4):
-            for block in ((512,) if G == 0 else (256, 512)):
+        for G in (-1, 0, 1, 2, 4):
+            for block in ((512,) if G <= 0 else (256, 512)):
                 mbr.hubbard_set_config(h, k, G, block)
                 y = torch.empty_like(x)
                 mbr.hubbard_apply(h, x, y)
@@ -313,8 +313,8 @@ def _shapes_equal(h, x, ks):
 def test_every_launch_shape_gives_identical_products():
     """Each row sums its terms in the same order and with the same fused
     operations whatever (k, G, block), the alpha_dn-stationary kernel (G = 0)
-    included, so the products are bitwise equal; the autotuner's choice is
-    one of them."""
+    and the flat kernel (G = -1) included, so the products are bitwise equal;
+    the autotuner's choice is one of them."""
     L = 14
     h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7), (6, 7)], U=[4.0] * L)
     x = torch.from_numpy(2 * synth.uniform01(21, h.dim) - 1).cuda()
@@ -323,7 +323,7 @@ def test_every_launch_shape_gives_identical_products():
         mbr.hubbard_set_config(h, 7, 3, 512)
     cfg = mbr.hubbard_autotune(h, reps=2)
     say("autotuned", cfg)
-    assert cfg["tuned_ms"] > 0 and cfg["G"] in (0, 1, 2, 4)
+    assert cfg["tuned_ms"] > 0 and cfg["G"] in (-1, 0, 1, 2, 4)
     y = torch.empty_like(x)
     mbr.hubbard_apply(h, x, y)
     assert torch.equal(y, ref)
@@ -366,7 +366,7 @@ def test_autotune_cache_roundtrip_and_corrupt_entries(tmp_path, monkeypatch):
     assert len(cache.read_text().splitlines()) == 3  # served from the cache
 
 
-@pytest.mark.parametrize("G,block", [(1, 256), (2, 512), (4, 256)])
+@pytest.mark.parametrize("G,block", [(1, 256), (2, 512), (4, 256), (-1, 512)])
 @pytest.mark.parametrize("reorth", [False, True])
 def test_lanczos_on_tile_kernel_launch_shapes(G, block, reorth):
     """Lanczos through the tile kernel's epilogue (G > 0): energies against
@@ -400,3 +400,77 @@ def test_lanczos_rejects_stale_launch_shape():
     mbr.hubbard_set_config(h, 3, 1, 256)
     with pytest.raises(mbr.MbrError):
         mbr.lanczos_step(lz, 1)
+
+
+@pytest.mark.parametrize("G", [-1, 0])
+def test_anderson_flat_and_rows_kernels_bitwise_equal_fp32(G):
+    """All 169 impurity-model sectors in fp32: the flat kernel (G = -1) and the
+    rows kernel (G = 0) give the same bits, sector sizes 1 to 853,776 and C_dn
+    from 1 to 924 included; the rows kernel result is the one checked against
+    the oracle row by row above."""
+    L = 12
+    eps_b, V = synth.anderson_parameters(5, 11)
+    eps = [-4.0] + list(eps_b)
+    U = [8.0] + [0.0] * 11
+    sectors = [(nu, nd) for nu in range(L + 1) for nd in range(L + 1)]
+    h = mbr.hubbard_create(L, OH.star_bonds(V), sectors, U=U, eps=eps, precision=mbr.F32)
+    x = torch.from_numpy(2 * synth.uniform01(5, h.dim) - 1).to(device="cuda", dtype=torch.float32)
+    cfg = mbr.hubbard_get_config(h)
+    ys = []
+    for g in (0, G):
+        mbr.hubbard_set_config(h, cfg["k"], g, 512)
+        y = torch.empty_like(x)
+        mbr.hubbard_apply(h, x, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+
+
+@pytest.mark.parametrize("L,sectors,prec", [(6, [(3, 3), (2, 4), (0, 3), (6, 6)], 0),
+                                            (8, [(4, 4), (3, 5)], 1)])
+def test_trie_ranked_product_bitwise_equals_halves(L, sectors, prec):
+    """The trie-ranked product (rank_kind = trie: full 2L-bit patterns ranked by
+    a packed trie, Sec. IV inside H·x) sums the same terms in the same order
+    as the staggered-halves kernels, so the products are bitwise equal; and
+    against the oracle row by row."""
+    bonds = OH.chain_bonds(L) + [(0, L // 2, 0.35)]
+    U = [3.0 + 0.1 * i for i in range(L)]
+    eps = [0.05 * i - 0.1 for i in range(L)]
+    ht = _check_apply(L, bonds, sectors, U, eps, prec, seed=L + 40, k=0)
+    x = _dev(2 * synth.uniform01(L + 41, ht.dim) - 1, prec)
+    hs = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps, precision=prec)
+    htr = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps, precision=prec, rank_kind=mbr.RANK_TRIE)
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    mbr.hubbard_apply(hs, x, y1)
+    mbr.hubbard_apply(htr, x, y2)
+    assert torch.equal(y1, y2)
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_set_config(htr, 3, 0, 512)
+
+
+@pytest.mark.timeout(600)
+def test_trie_ranked_product_chain_l14_bitwise_and_lanczos():
+    """Headline chain with trie ranks (k = 7, four levels): the whole product is
+    bitwise equal to the staggered-halves product, and 200 Lanczos steps reach
+    the oracle's ground energy."""
+    L = 14
+    bonds = OH.chain_bonds(L)
+    hs = mbr.hubbard_create(L, bonds, [(7, 7)], U=[4.0] * L)
+    ht = mbr.hubbard_create(L, bonds, [(7, 7)], U=[4.0] * L, rank_kind=mbr.RANK_TRIE, k=7)
+    x = torch.from_numpy(2 * synth.uniform01(3, hs.dim) - 1).cuda()
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    mbr.hubbard_apply(hs, x, y1)
+    mbr.hubbard_apply(ht, x, y2)
+    assert torch.equal(y1, y2)
+    gold = json.load(open(os.path.join(GOLD, "hubbard_chain_L14.json")))
+    lz = mbr.lanczos_create(ht, 200)
+    mbr.lanczos_start(lz, torch.from_numpy(synth.start_vector(2, ht.dim)).cuda())
+    mbr.lanczos_step(lz, 200)
+    e0, _ = mbr.lanczos_result(lz)
+    assert abs(e0[0] - gold["e0_exact"]) <= 1e-9 * abs(gold["e0_exact"])
+
+
+def test_trie_ranked_rejects_wide_patterns_and_bad_kind():
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_create(16, OH.chain_bonds(16), [(1, 1)], rank_kind=mbr.RANK_TRIE, k=2)
+    with pytest.raises(mbr.MbrError):
+        mbr.hubbard_create(4, OH.chain_bonds(4), [(2, 2)], rank_kind=7)

@@ -115,3 +115,83 @@ def test_trie_rejects_bad_args():
         mbr.build_trie(s, 0)
     with pytest.raises(mbr.MbrError):
         mbr.build_trie(s, 17)
+
+
+def _bt_check(M, cons, k, width=32, n_noise=20000, seed=1):
+    """Bitmap trie: every member ranks to its position, seeded arbitrary
+    patterns (bits above M included) agree with the oracle's bisection, and
+    the records per level are the distinct prefixes of the list."""
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons, width_bits=width)
+    r = mbr.build_bitmap_trie(s, k)
+    info = r.info()
+    H = -(-M // k)
+    assert info.kind == mbr.RANKER_BITMAP_TRIE and info.levels == H
+    recs, rbytes, lds = mbr.bitmap_trie_levels(r)
+    widths = [M - (H - 1) * k] + [k] * (H - 1)
+    above = M
+    for l in range(H):
+        above -= widths[l]                        # bits below and in chunk l
+        pre = st >> np.uint64(above + widths[l]) if above + widths[l] < 64 else np.zeros_like(st)
+        assert recs[l] == np.unique(pre).size, (l, recs[l])
+        assert rbytes[l] == max(8, 1 << int(np.ceil(np.log2(4 + (1 << widths[l]) / 8))))
+    dev = dev_u32 if width == 32 else dev_u64
+    got = host_rank(mbr.rank_batch(r, dev(st)))
+    assert np.array_equal(got, np.arange(st.size))
+    lim = (1 << min(M + 1, 64)) - 1 if M < 64 else (1 << 64) - 1
+    noise = synth.splitmix64(seed + M * 31 + k, n_noise) & np.uint64(lim)
+    q = np.concatenate([noise, st[::max(1, st.size // 700)] ^ np.uint64(1)])
+    if M < width:
+        q = np.concatenate([q, st[: min(500, st.size)] | np.uint64(1 << M)])
+    got = host_rank(mbr.rank_batch(r, dev(q)))
+    assert np.array_equal(got, OC.bisect_rank(st, q))
+    return r
+
+
+@pytest.mark.parametrize("M,N,k", [(6, 2, 2), (12, 6, 1), (13, 5, 3), (16, 8, 4), (16, 8, 5), (17, 8, 6),
+                                   (20, 10, 7), (24, 12, 8), (9, 0, 4), (9, 9, 4), (28, 1, 8)])
+def test_bitmap_trie_particle_number_sectors(M, N, k):
+    say("bitmap trie", M, N, k)
+    _bt_check(M, OC.constraints(M, N), k)
+
+
+@pytest.mark.parametrize("k", [3, 5, 8])
+def test_bitmap_trie_irregular_and_wide(k):
+    _bt_check(20, OC.constraints(20, 10, [(0xFF, 6, 8)]), k)
+    _bt_check(18, [(0x3FFFF, 7, 9), (0x5555, 2, 5)], k)
+    _bt_check(24, OC.spin_constraints(12, 6, 5), k)
+    _bt_check(40, OC.constraints(40, 3, [(0xF, 1, 2)]), k, width=64)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_bitmap_trie_ras_m32_full_size(k):
+    """The general-sector workload: M = 32, N = 16 with >= 6 of orbitals 0-7
+    occupied (66,110,671 states), 2^24 queries, 90% members and 10% non-members
+    (popcount 16, at most 5 of orbitals 0-7), as for the packed trie."""
+    M = 32
+    cons = OC.constraints(M, 16, [(0xFF, 6, 8)])
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons)
+    r = mbr.build_bitmap_trie(s, k)
+    say("ras bitmap trie k", k, "bytes", r.info().bytes, mbr.bitmap_trie_levels(r))
+    nq = 1 << 24
+    nm = nq // 10
+    idx = synth.uniform_indices(3, nq - nm, st.size)
+    pool = synth.random_subset_patterns(33, 3 * nm, 32, 16)
+    low = np.array([bin(int(v) & 0xFF).count("1") for v in pool])
+    non = pool[low <= 5][:nm]
+    q = np.concatenate([st[idx], non])
+    perm = synth.shuffle_positions(34, q.size)
+    q = q[perm]
+    want = np.concatenate([idx, np.full(nm, -1)])[perm]
+    assert np.array_equal(host_rank(mbr.rank_batch(r, dev_u32(q))), want)
+
+
+def test_bitmap_trie_rejects_bad_args():
+    s = mbr.sector_build(10, OC.constraints(10, 5))
+    for k in (0, 9):
+        with pytest.raises(mbr.MbrError):
+            mbr.build_bitmap_trie(s, k)
+    e = mbr.sector_build(10, [((1 << 10) - 1, 4, 4), (0x3, 3, 3)])
+    with pytest.raises(mbr.MbrError):
+        mbr.build_bitmap_trie(e, 4)
