@@ -368,6 +368,10 @@ def row_trie(torch, mbr, reps):
                                "roofline": hbm_roofline(136.0 * nq, ms, "bt_rank_kernel at the survey's "
                                                                         "136 B per query")}
         del r
+    # a plain copy of the 64 MB query array: known bytes, to calibrate the
+    # hardware traffic counters of the kernels above in the same run
+    qc = q.clone()
+    del qc
     # the learned ranker's search without its network, on the same queries
     r = mbr.build_sampled_ranker(s)
     ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)

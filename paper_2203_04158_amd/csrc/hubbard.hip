@@ -499,6 +499,7 @@ constexpr int kRowsMaxR = 4;          // alpha_dn per lane
 constexpr int kUpMax = 8;             // up-hop gathers in flight per row (more run in a tail loop)
 constexpr int kRowsDownFixed = 12;    // down-hop entries summed without a branch (padding adds zeros)
 constexpr uint32_t kRowsMaxX = 4096;  // staged elements per tile (blocks of C_dn + 1): offsets fit 16 bits
+constexpr uint32_t kRowsSlots = 3;    // fp32: alpha_up blocks per tile when each takes a row slot (512 < C_dn <= 1024)
 static_assert(kRowsMaxX <= (uint32_t)(kRowsMaxR * kRowsBlock), "R slots cover a block");
 
 // LDS layout: rank table | bond amplitudes | on-site U | reduction scratch |
@@ -966,6 +967,82 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                         const uint64_t row = base + rd;
                         if constexpr (LZ) {
                             const T uu = lz_out(v, c1, c2, gp_[s], has_p);
+                            out[row] = uu;
+                            dot = __builtin_fma((double)xv, (double)uu, dot);
+                        } else {
+                            out[row] = v;
+                        }
+                    }
+                }
+            } else if (sizeof(T) == 4 && R <= (int)kRowsSlots && c.gp == 0) {
+                // Several alpha_up blocks per tile (C_dn <= 1024), one per row
+                // slot: lane tid owns alpha_dn = tid in every block, so its
+                // down-hop list, half state and energy serve all of them, and
+                // the up-hop gathers of block r + 1 are in flight while block r
+                // computes.  Same sums as the one-block path.
+                const int rd = tid;
+                const bool valid = rd < (int)cdn;
+                const int rc = valid ? rd : 0;
+                T gx[2][kUpMax], cfs[2][kUpMax], gp_[2];
+                uint32_t hl1[kWords];
+                uint32_t ga1 = 0;
+                T ge1 = 0;
+                const T *pp = has_p ? p : x;
+                if constexpr (kKeepHs) {
+                    // only slot 0's copies: tagged so that the one-block path reloads all
+                    const uint32_t tag = c.loff | 0x80000000u;
+                    if (tag != kept_loff || c.hs_dn != kept_hs) {
+                        if constexpr (kKeepDn) rows_load_list(slists + (size_t)rc * kWords, hlc[0]);
+                        gac[0] = a.hs_states[c.hs_dn + rc];
+                        gec[0] = (T)a.hs_energy[c.hs_dn + rc];
+                        kept_loff = tag;
+                        kept_hs = c.hs_dn;
+                    }
+                }
+                if constexpr (!kKeepDn) rows_load_list(slists + (size_t)rc * kWords, hl1);
+                if constexpr (!kKeepHs) {
+                    ga1 = a.hs_states[c.hs_dn + rc];
+                    ge1 = (T)a.hs_energy[c.hs_dn + rc];
+                }
+                const uint32_t(&hld)[kWords] = kKeepDn ? hlc[0] : hl1;
+                const uint32_t gad = kKeepHs ? gac[0] : ga1;
+                const T ged = kKeepHs ? gec[0] : ge1;
+                const int nblk = (int)c.nblk;
+                auto gather = [&](int g, int sl) {
+                    const uint32_t nu = __builtin_amdgcn_readfirstlane(un[g]);
+#pragma unroll
+                    for (int h = 0; h < kUpMax; ++h) {
+                        const bool hh = h < (int)nu;
+                        const uint32_t t = hh ? __builtin_amdgcn_readfirstlane(ut[g * kRowsNB + h]) : 0u;
+                        gx[sl][h] = xsec[(uint64_t)t * cdn + rc];
+                        cfs[sl][h] = hh ? uniform_val(uc[g * kRowsNB + h]) : (T)0;
+                    }
+                    if constexpr (LZ) gp_[sl] = pp[base + (uint64_t)g * cdn + rc];
+                };
+                gather(0, 0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= nblk) break;
+                    const int sl = r & 1;
+                    if (r + 1 < R && r + 1 < nblk) gather(r + 1, sl ^ 1);
+                    const unsigned char *xb = bb + (size_t)r * (cdn + 1) * sizeof(T);
+                    const T acc = rows_down<T, UT>(hld, xb, amp, valid);
+                    if (valid) {
+                        const uint32_t nu = __builtin_amdgcn_readfirstlane(un[r]);
+                        const uint32_t au = __builtin_amdgcn_readfirstlane(ua[r]);
+                        const T eu = uniform_val(ue[r]);
+                        const T xv = reinterpret_cast<const T *>(xb)[rd];
+                        const T dg = eu + ged + rows_u_energy<T>(au & gad, a, ul);
+                        T v = fma_t(dg, xv, UT ? tu * acc : acc);
+#pragma unroll
+                        for (int h = 0; h < kUpMax; ++h) v = fma_t(cfs[sl][h], gx[sl][h], v);
+                        for (uint32_t h = kUpMax; h < nu; ++h)
+                            v = fma_t(uniform_val(uc[r * kRowsNB + h]),
+                                      xsec[(uint64_t)__builtin_amdgcn_readfirstlane(ut[r * kRowsNB + h]) * cdn + rd],
+                                      v);
+                        const uint64_t row = base + (uint64_t)r * cdn + rd;
+                        if constexpr (LZ) {
+                            const T uu = lz_out(v, c1, c2, gp_[sl], has_p);
                             out[row] = uu;
                             dot = __builtin_fma((double)xv, (double)uu, dot);
                         } else {
@@ -1567,11 +1644,25 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
         } else if (sc.rows) {
             sc.wide = 1;
             sc.x_lds = 1;
-            sc.gp = sc.cdn <= (uint32_t)kRowsBlock / 2 ? std::min<uint32_t>(kRowsMaxG, kRowsBlock / sc.cdn) : 1;
-            sc.R = sc.gp > 1 ? 1 : (sc.cdn + kRowsBlock - 1) / kRowsBlock;
+            if (sc.cdn <= (uint32_t)kRowsBlock / 2) {
+                // blocks across lanes
+                sc.gp = std::min<uint32_t>(kRowsMaxG, kRowsBlock / sc.cdn);
+                sc.R = 1;
+                nblk = sc.gp;
+            } else if (sc.cdn <= (uint32_t)kRowsBlock && tsz == 4) {
+                // one block per row slot (gp = 0): kRowsSlots blocks a tile
+                // (fp32; in fp64 the extra slots would not fit the registers)
+                sc.gp = 0;
+                nblk = std::min<uint32_t>(kRowsSlots, kRowsMaxX / (sc.cdn + 1));
+                sc.R = nblk;
+            } else {
+                // one block per tile, spread over ceil(C_dn / 1024) row slots
+                sc.gp = 1;
+                sc.R = (sc.cdn + kRowsBlock - 1) / kRowsBlock;
+                nblk = 1;
+            }
             rows_R = std::max(rows_R, (int)sc.R);
-            rows_gmax = std::max(rows_gmax, sc.gp);
-            nblk = sc.gp;
+            rows_gmax = std::max(rows_gmax, std::max<uint32_t>(sc.gp, nblk));
         } else {
             sc.wide = sc.cdn >= kWideMin;
             if (sc.wide) {

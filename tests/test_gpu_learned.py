@@ -311,3 +311,40 @@ def test_learned_and_sampled_m32_8x8_full_size():
         say("m32 8+8 all members:", name)
         assert torch.equal(mbr.rank_batch(r, states), idx), name
         assert np.array_equal(host_rank(mbr.rank_batch(r, dev_u32(q))), want), name
+
+
+def test_learned_windows_narrow_the_search():
+    """What the trained network gains over the same search without it, in
+    probes: the search narrows a window by 16x per sampled level, so a window
+    of w states needs ceil(log16 w) levels and the whole list
+    ceil(log16 N_s).  On the (7,7) chain sector, trained as in the benchmark,
+    the members' own leaf windows (recomputed on the host from the query-time
+    network outputs) save at least half a level on average and are at least
+    ten times narrower than the list.  Throughput is the bench's business:
+    there the network's forward pass costs more than the saved levels."""
+    M, cons = 28, OC.spin_constraints(14, 7, 7)
+    s = mbr.sector_build(M, cons)
+    sampled = mbr.build_sampled_ranker(s)
+    lr_ = mbr.learned_train(s, sampled, epochs=8, batch=4096, lr=2e-3, seed=4,
+                            samples_per_epoch=1 << 22, max_window=1 << 31)
+    info = mbr.learned_stats(lr_)
+    st = s.states()
+    n = s.size
+    pad = (-n) % 64
+    q = torch.cat([st, torch.zeros(pad, dtype=torch.int32, device="cuda")])
+    params = torch.from_numpy(mbr.learned_params(lr_)).cuda()
+    y = mbr.mlp_forward(params, q).cpu().numpy()[:n]
+    b, lo, hi = _leaf_windows(y, info["n_leaves"], n)
+    w = (hi[b] - lo[b] + 1).astype(np.float64)
+    assert abs(w.mean() - info["mean_window"]) <= 1e-9 * info["mean_window"]
+    lv_learned = np.ceil(np.log(np.maximum(w, 1)) / np.log(16))
+    lv_whole = np.ceil(np.log(n) / np.log(16))
+    saved = lv_whole - lv_learned.mean()
+    say("chain: whole-list levels", lv_whole, "learned levels (mean)", lv_learned.mean(),
+        "mean window", w.mean(), "of", n)
+    assert w.mean() * 10 <= n
+    assert saved >= 0.5
+    # and the answers of both stay exact
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    assert torch.equal(mbr.rank_batch(lr_, st), idx)
+    assert torch.equal(mbr.rank_batch(sampled, st), idx)
