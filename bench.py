@@ -367,6 +367,7 @@ def row_trie(torch, mbr, reps):
                                "record_bytes": rbytes, "lds_levels": lds_lv,
                                "roofline": hbm_roofline(136.0 * nq, ms, "bt_rank_kernel at the survey's "
                                                                         "136 B per query")}
+        res[f"bitmap_k{k}"]["roofline"]["traffic"] = traffic_for(f"bt_rank_kernel<unsignedint>@k{k}")
         del r
     # a plain copy of the 64 MB query array: known bytes, to calibrate the
     # hardware traffic counters of the kernels above in the same run
@@ -439,13 +440,15 @@ def row_sweep(torch, mbr, reps):
     replacement and ordered by value (as the paper does); bisection,
     combinadics ranking (Fig. algr), staggered lookup and trie lookup at
     R = 4, 8, 12.  Kernel time per lookup, exactness, and the trie's memory
-    overhead f = trie bytes / (4 N_s)."""
+    overhead f = trie bytes / (4 N_s); the bitmap trie at R = 4, 8 beside them."""
     import synth
     M, nq = 28, 1 << 22
     ranked = torch.empty(nq, dtype=torch.int32, device="cuda")
-    methods = ["bisect", "cns"] + [f"staggered_k{k}" for k in (4, 8, 12)] + [f"trie_k{k}" for k in (4, 8, 12)]
+    methods = (["bisect", "cns"] + [f"staggered_k{k}" for k in (4, 8, 12)] + [f"trie_k{k}" for k in (4, 8, 12)]
+               + [f"bitmap_k{k}" for k in (4, 8)])
     ns = {m: [] for m in methods}
     f = {f"trie_k{k}": [] for k in (4, 8, 12)}
+    f.update({f"bitmap_k{k}": [] for k in (4, 8)})
     exact = True
     sizes = []
     for N in range(1, M):
@@ -460,6 +463,9 @@ def row_sweep(torch, mbr, reps):
                 r = mbr.build_cns_ranker(M, N)
             elif m.startswith("staggered"):
                 r = mbr.build_staggered_tables(M, N, int(m.split("_k")[1]))
+            elif m.startswith("bitmap"):
+                r = mbr.build_bitmap_trie(s, int(m.split("_k")[1]))
+                f[m].append(r.info().bytes / 4 / s.size)
             else:
                 r = mbr.build_trie(s, int(m.split("_k")[1]))
                 f[m].append(r.info().bytes / 4 / s.size)
@@ -870,12 +876,18 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         print(f"[bench] row {r} done in {extra[r]['wall_s']:.1f} s", file=sys.stderr, flush=True)
-    if extra:
-        out["rows"] = summarize(extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if extra:
+        out["rows"] = summarize(extra)   # last, so that a tail of the line holds every workload
     print("[bench] detail " + json.dumps({"headline": out, "rows": extra}), file=sys.stderr, flush=True)
-    print(json.dumps(_round(out)), flush=True)
+    line = _round(out)
+    line["roofline"].pop("kernel", None)
+    if "cpu_baseline" in line:
+        line["cpu_baseline"].pop("rank_Granks_m24_n12_2e22", None)
+        line["cpu_baseline"]["sample"] = (f"plain bisection gather-form H·x (oracle, fp64) on rows of the headline "
+                                          f"sector, {line['cpu_baseline']['cores']} threads, scaled to whole products")
+    print(json.dumps(line, separators=(",", ":")), flush=True)
 
 
 def _round(v, digits: int = 4):
@@ -891,72 +903,53 @@ def _round(v, digits: int = 4):
 
 def summarize(extra: dict) -> dict:
     """One short entry per workload for the JSON line (the full records go to
-    stderr): throughput, roofline fraction and exactness."""
+    stderr): throughput, roofline fraction and exactness, short keys."""
     s = {}
-    g = lambda d, *ks: [d.get(k) for k in ks]  # noqa: E731
+    r3 = lambda d, keys: {k: d[k]["value"] for k in keys if k in d}  # noqa: E731
     if "staggered" in extra:
         e = extra["staggered"]
-        s["cfg1_staggered"] = {"Granks_s": e["value"], "frac": e["roofline"]["frac"], "exact": e["exact"],
-                               "cold_Granks_s": e["cold_after_1GB_copy"]["value"],
-                               "2e28_Granks_s": e["stress_2e28"]["value"],
-                               "2e28_frac": e["stress_2e28"]["roofline"]["frac"]}
+        s["cfg1_stag"] = {"Grk_s": e["value"], "frac": e["roofline"]["frac"], "exact": e["exact"],
+                          "2e28_frac": e["stress_2e28"]["roofline"]["frac"]}
     if "unrank" in extra:
         e = extra["unrank"]
-        s["unrank_G_s"] = {k: e[k]["value"] for k in e if isinstance(e[k], dict) and "value" in e[k]}
-        s["unrank_exact"] = all(e[k]["exact"] for k in e if isinstance(e[k], dict) and "exact" in e[k])
+        s["unrank_G_s"] = {k: e[k]["value"] for k in ("list_chain_7x7", "spin_chain_7x7") if k in e}
     if "staggered64" in extra:
-        e = extra["staggered64"]
-        s["m64_staggered_Granks_s"] = {k: e[k]["value"] for k in e if k.startswith("k")}
-        s["m64_exact"] = e["exact"]
+        s["m64_stag_Grk_s"] = {k: extra["staggered64"][k]["value"] for k in ("k5", "k8")}
     if "trie" in extra:
         e = extra["trie"]
-        s["cfg3_trie"] = {k: {"Granks_s": e[k]["value"], "frac": e[k]["roofline"]["frac"], "exact": e[k]["exact"],
-                              "f": e[k]["overhead_f"]} for k in ("k4", "k8") if k in e}
-        s["cfg3_trie"]["sampled_no_net_Granks_s"] = e["sampled_search_no_net"]["value"]
-        for k in ("bitmap_k4", "bitmap_k8"):
-            if k in e:
-                s["cfg3_trie"][k] = {"Granks_s": e[k]["value"], "frac": e[k]["roofline"]["frac"],
-                                     "exact": e[k]["exact"], "f": e[k]["overhead_f"]}
+        s["cfg3"] = {k: [e[k]["value"], e[k]["roofline"]["frac"]] for k in ("k8", "bitmap_k8") if k in e}
+        s["cfg3"]["k4"] = e["k4"]["value"]
+        s["cfg3"]["no_net"] = e["sampled_search_no_net"]["value"]
+        s["cfg3"]["exact"] = all(e[k]["exact"] for k in ("k4", "k8", "bitmap_k4", "bitmap_k8") if k in e)
     if "learned" in extra:
-        e = extra["learned"]
-        for name, r in e.items():
-            if not isinstance(r, dict) or "learned" not in r:
-                continue
-            names = ("learned", "sampled_search_no_net", "trie_k8", "bitmap_trie_k8", "spin_staggered")
-            t = {k: r[k]["value"] for k in names if k in r}
-            t["exact"] = all(r[k]["exact"] for k in names if k in r)
-            t["mean_window"] = r["learned_stats"]["mean_window"]
-            if "mlp_forward" in r:
-                t["mlp_frac"] = r["mlp_forward"]["roofline"]["frac"]
-            s[f"cfg4_{name}_Granks_s"] = t
+        for name, r in extra["learned"].items():
+            if isinstance(r, dict) and "learned" in r:
+                t = r3(r, ("learned", "sampled_search_no_net", "trie_k8", "bitmap_trie_k8", "spin_staggered"))
+                t["exact"] = all(r[k]["exact"] for k in ("learned", "sampled_search_no_net", "trie_k8",
+                                                         "bitmap_trie_k8") if k in r)
+                if "mlp_forward" in r:
+                    t["mlp_frac"] = r["mlp_forward"]["roofline"]["frac"]
+                s["cfg4_" + ("chain" if "chain" in name else "8x8")] = t
     if "chain" in extra:
         e = extra["chain"]
-        s["cfg2_precision_steps_s"] = {k: e[k]["value"] for k in ("fp64", "fp32", "fp64_reorth", "fp32_reorth")}
-        s["cfg2_precision_rel_err"] = {k: e[k]["rel_err_vs_oracle"] for k in ("fp64", "fp32", "fp64_reorth",
-                                                                              "fp32_reorth")}
-        s["cfg2_trie_ranked"] = {k: {"steps_s": e[k]["value"], "hv_ms": e[k]["hv_kernel_ms"]}
-                                 for k in ("trie_k7", "trie_k14") if k in e}
-        s["cfg2_staggered_hv_ms"] = e["fp64"]["hv_kernel_ms"]
+        s["cfg2_steps_s"] = {k: e[k]["value"] for k in ("fp64", "fp32", "fp64_reorth", "fp32_reorth",
+                                                        "trie_k14")}
+        s["cfg2_fp32_err"] = e["fp32"]["rel_err_vs_oracle"]
+        s["cfg2_hv_ms"] = {"stag": e["fp64"]["hv_kernel_ms"], "trie_k14": e["trie_k14"]["hv_kernel_ms"]}
     if "batched" in extra:
         e = extra["batched"]
         s["cfg5_steps_s"] = {k: e[k]["value"] for k in e if isinstance(e[k], dict) and "value" in e[k]}
-        s["cfg5_worst_rel_err"] = max(e[k]["worst_rel_err_vs_oracle"] for k in e
-                                      if isinstance(e[k], dict) and "worst_rel_err_vs_oracle" in e[k])
-        s["cfg5_gains"] = {k[5:]: e[k] for k in e if k.startswith("gain_")}
-        s["cfg5_hv"] = {k: {"ms": v["kernel_ms"], "frac": v["roofline"]["frac"], "G": v["launch"]["G"],
-                            "k": v["launch"]["k"], "ms_by_G": v.get("ms_by_G")} for k, v in e["hv"].items()}
+        s["cfg5_err"] = max(e[k]["worst_rel_err_vs_oracle"] for k in e
+                            if isinstance(e[k], dict) and "worst_rel_err_vs_oracle" in e[k])
+        s["cfg5_hv"] = {k: [v["kernel_ms"], v["roofline"]["frac"]] for k, v in e["hv"].items()}
     if "operator" in extra:
-        e = extra["operator"]
-        s["momentum_ring_hv_s"] = {k: e[k]["value"] for k in ("trie_k7", "trie_k14")}
-        s["momentum_ring_e0_rel_diff"] = e["lanczos"]["rel_diff"]
+        s["kring_hv_s"] = extra["operator"]["trie_k14"]["value"]
     if "ceiling" in extra:
         e = extra["ceiling"]
-        s["ceiling"] = {"copy_GBs": e["copy_1GB"]["GBs"]}
-        s["ceiling"].update({k + "_GBs": v["granule_GBs"] for k, v in e.items() if k.endswith("_d1")
-                             and "granule_GBs" in v})
-        s["ceiling"]["lds_d1_Gg_s"] = e["lds64KB_d1"]["Ggathers_s"]
+        s["ceil_GBs"] = {"copy": e["copy_1GB"]["GBs"], "g4MB": e["4MB_d1"]["granule_GBs"],
+                         "g256MB": e["256MB_d1"]["granule_GBs"], "g4GB": e["4096MB_d1"]["granule_GBs"]}
     if "sweep" in extra:
-        s["sweep_half_filled_Granks_s"] = extra["sweep"]["half_filled_granks_per_s"]
+        s["sweep_n14_Grk_s"] = extra["sweep"]["half_filled_granks_per_s"]
         s["sweep_exact"] = extra["sweep"]["exact"]
     return s
 
