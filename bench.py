@@ -243,9 +243,14 @@ def row_staggered(torch, mbr, reps):
               "exact": bool(torch.equal(big_out, idx.repeat(64))),
               "roofline": hbm_roofline(8.0 * big_q.numel(), ms_big, "rank_staggered_kernel, 2^28 queries")}
     del big_q, big_out
+    # the rank-side autotuner's pick of k for this sector and these queries
+    rt, tune = mbr.rank_autotune(s, mbr.RANKER_STAGGERED, q, reps=reps)
+    ms_t = time_launches(torch, lambda: mbr.rank_batch(rt, q, out=out), reps)
+    autotuned = {"k": tune["k"], "candidates_timed": tune["tried"], "kernel_ms": ms_t,
+                 "value": nq / (ms_t * 1e-3) / 1e9, "exact": bool(torch.equal(out, idx))}
     return {"workload": "sector M=24 N=12 (2,704,156 states), 2^22 uniform member queries, k=8",
             "value": nq / (ms * 1e-3) / 1e9, "unit": "Granks/s", "kernel_ms": ms, "exact": exact,
-            "roofline": roof, "cold_after_1GB_copy": cold_res, "stress_2e28": stress}
+            "roofline": roof, "cold_after_1GB_copy": cold_res, "stress_2e28": stress, "autotuned": autotuned}
 
 
 def row_unrank(torch, mbr, reps):
@@ -910,6 +915,8 @@ def summarize(extra: dict) -> dict:
         e = extra["staggered"]
         s["cfg1_stag"] = {"Grk_s": e["value"], "frac": e["roofline"]["frac"], "exact": e["exact"],
                           "2e28_frac": e["stress_2e28"]["roofline"]["frac"]}
+        if "autotuned" in e:
+            s["cfg1_stag"]["tuned_k"] = e["autotuned"]["k"]
     if "unrank" in extra:
         e = extra["unrank"]
         s["unrank_G_s"] = {k: e[k]["value"] for k in ("list_chain_7x7", "spin_chain_7x7") if k in e}

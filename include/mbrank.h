@@ -199,9 +199,11 @@ mbr_status mbr_build_trie(const mbr_sector *s, int32_t k, mbr_ranker **out, void
 
 /* Bitmap trie (the radix-2^k trie of Sec. IV in a GPU layout): chunks
  * dispatched from the most significant end (the top chunk holds M mod k bits
- * when k does not divide M), every node one record of a 32-bit base and a
- * 2^k-bit map of the chunk values that occur under it, 8, 16, 32 or 64 bytes
- * (k <= 5, 6, 7, 8) aligned to its size.  The child for chunk value c is
+ * when k does not divide M), every node one record of a 32-bit base, for
+ * k >= 6 the set-bit counts before each 32-bit word of the map (one byte
+ * each), and a 2^k-bit map of the chunk values that occur under it: 8, 16, 32
+ * or 64 bytes (k <= 5, 6, 7, 8; the same size on every level) aligned to its
+ * size.  The child for chunk value c is
  * record base + (set bits below c) of the next level; at the last level that
  * count gives the rank (base = position of the node's first member).  A clear
  * bit means the pattern is not in the sector, so no state list is read.
@@ -275,6 +277,18 @@ mbr_status mbr_build_sampled_ranker(const mbr_sector *s, mbr_ranker **out, void 
  * whether it answers through its own window search (1) or the fallback (0). */
 mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses_window);
 
+/* Tune the learned ranker's fallback threshold on the caller's queries: time
+ * its window search and its fallback ranker (one untimed launch, then `reps`
+ * launches each, 1..1000) on the n device queries d_q and keep the faster for
+ * later calls; both give the same ranks, since the window search is exact
+ * for any e.  The threshold is then e when the window search wins (it
+ * serves) and e - 1 otherwise (the fallback serves).  *ms_window and
+ * *ms_fallback (either may be NULL) receive the two average times.  EINVAL
+ * for a ranker without a fallback or of another kind.  Synchronises
+ * `stream`. */
+mbr_status mbr_learned_autotune(mbr_ranker *r, const void *d_q, uint64_t n, int32_t reps,
+                                double *ms_window, double *ms_fallback, void *stream);
+
 typedef struct {
     uint64_t n_leaves;            /* stage-2 leaves (a power of two) */
     uint64_t max_window;          /* widest leaf window hi - lo (= e) */
@@ -328,6 +342,35 @@ mbr_status mbr_rank_batch64(const mbr_ranker *r, const void *d_q, uint64_t n, ui
                             void *stream);
 
 mbr_status mbr_ranker_destroy(mbr_ranker *r);
+
+/* Rank-side autotuner: the chunk width k (the paper's R, Sec. V.A, where the
+ * fastest width is a property of the machine) of one ranker kind for one
+ * sector.  kind is MBR_RANKER_STAGGERED (the sector must be exactly C(M, N):
+ * one window on all M bits with lo == hi, else EINVAL), MBR_RANKER_TRIE or
+ * MBR_RANKER_BITMAP_TRIE.  Candidates are ks[0..n_ks) (n_ks <= 64), or with
+ * n_ks = 0 {3,4,5,6,7,8,10,12,14,16}, {4,6,8,10,12} and {4,...,8} for the
+ * three kinds; each is capped at M.  Every candidate is built and timed on the
+ * caller's n device queries d_q (one untimed launch, then `reps` launches,
+ * 1..1000, HIP events on `stream`); candidates that cannot be built or run
+ * (device memory, ranks beyond 32 bits) are skipped, and when none is left
+ * the first failure is returned.  *out receives the fastest ranker (the
+ * caller destroys it; trie kinds keep a reference to `s`), *res its k and
+ * average time.  If the environment variable MBR_AUTOTUNE_CACHE names a
+ * file, an entry for this device, kind and sector description (M, width,
+ * size, windows, modular weight) is used without timing and new results are
+ * appended; sectors adopted from a list are never cached; malformed entries
+ * are ignored.  Synchronises `stream`. */
+typedef struct {
+    int32_t kind;       /* the ranker kind tuned */
+    int32_t k;          /* the chosen chunk width */
+    double ms;          /* its time for one mbr_rank_batch of the n queries (the cached time on a hit) */
+    int32_t from_cache; /* 1: read from MBR_AUTOTUNE_CACHE, nothing timed */
+    int32_t tried;      /* candidates built and timed */
+} mbr_rank_tuning;
+
+mbr_status mbr_rank_autotune(const mbr_sector *s, int32_t kind, const int32_t *ks, int32_t n_ks,
+                             const void *d_q, uint64_t n, int32_t reps, mbr_rank_tuning *res,
+                             mbr_ranker **out, void *stream);
 
 /* ======================================================================== */
 /* General operators from non-branching terms (Sec. II, Eq. H, App. A)       */
@@ -438,8 +481,9 @@ typedef struct {
  * pattern from the list and ranks every hop target by a trie walk (a hop
  * target of a spin sector is always a member, so no membership read).  Both
  * kinds sum each row's terms in the same order, so their products are
- * bitwise equal; the trie kind has one launch shape (set_config and autotune
- * return EUNSUPPORTED). */
+ * bitwise equal.  The trie kind has one launch shape (set_config returns
+ * EUNSUPPORTED); its autotune times the trie chunk widths that give two,
+ * three and four levels and keeps the fastest. */
 mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void *stream);
 
 /* Total dimension and, if offsets != NULL, the n_sectors+1 sector offsets. */
@@ -481,7 +525,8 @@ mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg);
 mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream);
 
 /* Time every supported (k, G, block) on this device with `reps` products of
- * scratch vectors and keep the fastest.  If the environment variable
+ * scratch vectors and keep the fastest (for a trie-ranked product: the trie's
+ * chunk width, rebuilding the tries; get_config then reports it as k).  If the environment variable
  * MBR_AUTOTUNE_CACHE names a file, a matching entry (device, L, bonds,
  * sectors, precision) is used without timing, and new results are appended;
  * unreadable or malformed entries are ignored.  Synchronises `stream`. */

@@ -52,6 +52,11 @@ class LearnedInfo(C.Structure):
                 ("single_window_error", C.c_uint64), ("uses_window", C.c_int32)]
 
 
+class RankTuning(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("ms", C.c_double), ("from_cache", C.c_int32),
+                ("tried", C.c_int32)]
+
+
 class Term(C.Structure):
     _fields_ = [("v", C.c_double), ("m", C.c_uint64), ("l", C.c_uint64), ("r", C.c_uint64),
                 ("x", C.c_uint64), ("s", C.c_uint64)]
@@ -115,6 +120,10 @@ _SIGS = {
     "mbr_learned_max_error": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64),
                                           C.POINTER(C.c_int32)]),
     "mbr_learned_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbr_learned_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "mbr_rank_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64,
+                                      C.c_int32, C.POINTER(RankTuning), C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_learned_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mbr_sector_build_mod": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                          C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
@@ -434,6 +443,29 @@ def learned_max_error(ranker: Ranker):
     w = C.c_int32()
     _check("mbr_learned_max_error", lib().mbr_learned_max_error(ranker.handle, C.byref(e), C.byref(w)))
     return int(e.value), bool(w.value)
+
+
+def learned_autotune(ranker: Ranker, queries, reps: int = 5, stream=None):
+    """Time the learned ranker's window search and its fallback on `queries`
+    (uint32 device tensor) and keep the faster; returns (ms_window, ms_fallback)."""
+    tw, tf = C.c_double(), C.c_double()
+    _check("mbr_learned_autotune", lib().mbr_learned_autotune(
+        ranker.handle, _dptr(queries), queries.numel(), reps, C.byref(tw), C.byref(tf), _stream(stream)))
+    return float(tw.value), float(tf.value)
+
+
+def rank_autotune(sector: Sector, kind: int, queries, ks=None, reps: int = 5, stream=None):
+    """Fastest chunk width of one ranker kind for `sector` on `queries` (device
+    tensor of the sector's width); returns (ranker, tuning dict)."""
+    res = RankTuning()
+    h = C.c_void_p()
+    karr = (C.c_int32 * len(ks))(*ks) if ks else None
+    _check("mbr_rank_autotune", lib().mbr_rank_autotune(
+        sector.handle, kind, karr, len(ks) if ks else 0, _dptr(queries), queries.numel(), reps,
+        C.byref(res), C.byref(h), _stream(stream)))
+    keep = (sector,) if kind in (RANKER_TRIE, RANKER_BITMAP_TRIE) else ()
+    return Ranker(h, keep=keep), {"kind": int(res.kind), "k": int(res.k), "ms": float(res.ms),
+                                  "from_cache": bool(res.from_cache), "tried": int(res.tried)}
 
 
 def learned_stats(ranker: Ranker) -> dict:

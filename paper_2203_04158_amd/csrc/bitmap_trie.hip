@@ -12,8 +12,12 @@
 // packed trie of trie.hip checks states[rank] == alpha after its walk).
 //
 // Records are 2^s bytes (8 B for k <= 5, 16 B for k = 6, 32 B for k = 7,
-// 64 B for k = 8: word 0 the base, then the 2^k bits), aligned to their size,
-// so a record never straddles a 64-byte line: one line per level and query.
+// 64 B for k = 8), the same size on every level (the root's short chunk
+// included, one record), aligned to their size, so a record never straddles a
+// 64-byte line: one line per level and query.  Word 0 is the base; for k >= 6
+// one (k = 6, 7) or two (k = 8) words follow with, in byte w, the set bits of
+// map words 0..w-1; then the 2^k-bit map.  A step reads the base, the prefix
+// byte and one map word, so it costs one popcount whatever k is.
 // The top levels that fit 48 KB are staged in LDS.  With k = 8 the sector
 // M = 32, N = 16 with >= 6 of orbitals 0-7 occupied needs about 4 M leaf
 // records (its packed trie holds 332 M entries).
@@ -34,62 +38,44 @@ struct BtArgs {
     const uint32_t *rec;      // all levels' records, level after level
     int32_t M, H, lds_levels;
     uint32_t lds_words;       // words of the staged levels
-    uint32_t rw[kMaxH];       // record words per level (2, 4, 8, 16)
     uint32_t off[kMaxH];      // first word of each level
     uint32_t shift[kMaxH];    // bit offset of each level's chunk
     uint32_t cmask[kMaxH];    // chunk mask
 };
 
-// One level of the walk: the record at `rec` (rw words), chunk value c.
+// Words before the map in a record of RW words: the base, and the prefix
+// bytes of the map words when there is more than one.
+__host__ __device__ constexpr int map_offset(int rw) { return rw == 2 ? 1 : rw == 16 ? 3 : 2; }
+
+// One level of the walk: the record at `rec` (RW words), chunk value c.
 // Returns whether c occurs; `next` receives base + set bits below c.
-__device__ __forceinline__ bool bt_step(const uint32_t *rec, uint32_t rw, uint32_t c, uint32_t &next) {
-    uint32_t w[16];
-    if (rw == 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 v = reinterpret_cast<const uint4 *>(rec)[q];
-            w[4 * q] = v.x;
-            w[4 * q + 1] = v.y;
-            w[4 * q + 2] = v.z;
-            w[4 * q + 3] = v.w;
-        }
+template <int RW>
+__device__ __forceinline__ bool bt_step(const uint32_t *rec, uint32_t c, uint32_t &next) {
+    const uint32_t bit = c & 31;
+    uint32_t base, cw, pre;
+    if constexpr (RW == 2) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(rec);
+        base = v.x;
+        cw = v.y;
+        pre = 0;
     } else {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) w[i] = 0;
-        if (rw == 8) {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const uint4 v = reinterpret_cast<const uint4 *>(rec)[q];
-                w[4 * q] = v.x;
-                w[4 * q + 1] = v.y;
-                w[4 * q + 2] = v.z;
-                w[4 * q + 3] = v.w;
-            }
-        } else if (rw == 4) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(rec);
-            w[0] = v.x;
-            w[1] = v.y;
-            w[2] = v.z;
-            w[3] = v.w;
+        const uint4 h = *reinterpret_cast<const uint4 *>(rec);  // base, prefix words (and map words for k = 6)
+        const uint32_t word = c >> 5;
+        uint32_t pw = h.y;
+        if constexpr (RW == 4) {
+            cw = word ? h.w : h.z;
         } else {
-            const uint2 v = *reinterpret_cast<const uint2 *>(rec);
-            w[0] = v.x;
-            w[1] = v.y;
+            cw = rec[map_offset(RW) + word];
+            if constexpr (RW == 16) pw = word >= 4 ? h.z : h.y;
         }
+        pre = (pw >> (8 * (word & 3))) & 0xffu;
+        base = h.x;
     }
-    const uint32_t word = c >> 5, bit = c & 31;
-    uint32_t below = 0, cw = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        below += (uint32_t)i < word ? (uint32_t)__popc(w[1 + i]) : 0u;
-        cw = (uint32_t)i == word ? w[1 + i] : cw;
-    }
-    below += __popc(cw & ((1u << bit) - 1u));
-    next = w[0] + below;
+    next = base + pre + __popc(cw & ((1u << bit) - 1u));
     return (cw >> bit) & 1u;
 }
 
-template <class P>
+template <class P, int RW>
 __global__ void __launch_bounds__(kBlock) bt_rank_kernel(const P *__restrict__ q, uint64_t n,
                                                          uint32_t *__restrict__ out, BtArgs a) {
     extern __shared__ __align__(16) uint32_t top[];
@@ -115,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) bt_rank_kernel(const P *__restrict__ q
             for (int u = 0; u < kQ; ++u) {
                 uint32_t nx;
                 const uint32_t c = (uint32_t)(x[u] >> a.shift[l]) & a.cmask[l];
-                ok[u] = bt_step(top + a.off[l] + node[u] * a.rw[l], a.rw[l], c, nx) && ok[u];
+                ok[u] = bt_step<RW>(top + a.off[l] + node[u] * RW, c, nx) && ok[u];
                 node[u] = ok[u] ? nx : 0u;
             }
         }
@@ -125,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) bt_rank_kernel(const P *__restrict__ q
             for (int u = 0; u < kQ; ++u) {
                 uint32_t nx;
                 const uint32_t c = (uint32_t)(x[u] >> a.shift[l]) & a.cmask[l];
-                ok[u] = bt_step(lv + node[u] * a.rw[l], a.rw[l], c, nx) && ok[u];
+                ok[u] = bt_step<RW>(lv + node[u] * RW, c, nx) && ok[u];  // words < 2^32
                 node[u] = ok[u] ? nx : 0u;
             }
         }
@@ -137,8 +123,12 @@ __global__ void __launch_bounds__(kBlock) bt_rank_kernel(const P *__restrict__ q
     }
 }
 
+// Words of a record for k-bit chunks: base, prefix words, map, rounded up to
+// a power of two.
 uint32_t record_words(int w) {
-    const uint32_t bytes = 4 + ((1u << w) + 7) / 8;
+    const uint32_t map_words = ((1u << w) + 31) / 32;
+    const uint32_t pref_words = map_words > 1 ? (map_words + 3) / 4 : 0;
+    const uint32_t bytes = 4 * (1 + pref_words + map_words);
     uint32_t r = 8;
     while (r < bytes) r *= 2;
     return r / 4;
@@ -162,8 +152,9 @@ mbr_status build_records(BitmapTrie &t, const std::vector<P> &s) {
         nodes[l] = cnt;
     }
     uint64_t words = 0;
+    const int kw = *std::max_element(t.w, t.w + H);
     for (int l = 0; l < H; ++l) {
-        t.rw[l] = record_words(t.w[l]);
+        t.rw[l] = record_words(kw);  // one record size for all levels (the root's short chunk included)
         words = (words + 15) & ~(uint64_t)15;  // every level starts on a 64-byte line
         t.off[l] = words;
         t.nodes[l] = nodes[l];
@@ -188,9 +179,22 @@ mbr_status build_records(BitmapTrie &t, const std::vector<P> &s) {
                 rec[t.off[l] + (uint64_t)cur[l] * t.rw[l]] = l + 1 < H ? (uint32_t)(cur[l + 1] + 1) : (uint32_t)i;
             }
             const uint32_t c = (uint32_t)(a >> t.shift[l]) & ((1u << t.w[l]) - 1u);
-            rec[t.off[l] + (uint64_t)cur[l] * t.rw[l] + 1 + (c >> 5)] |= 1u << (c & 31);
+            rec[t.off[l] + (uint64_t)cur[l] * t.rw[l] + map_offset(t.rw[l]) + (c >> 5)] |= 1u << (c & 31);
         }
     }
+    // prefix bytes: set bits of the map words before each word
+    const uint32_t map_words = ((1u << kw) + 31) / 32;
+    if (map_words > 1)
+        for (int l = 0; l < H; ++l)
+            for (uint64_t nd = 0; nd < nodes[l]; ++nd) {
+                uint32_t *r = rec.data() + t.off[l] + nd * t.rw[l];
+                const uint32_t *m = r + map_offset(t.rw[l]);
+                uint32_t run = 0;
+                for (uint32_t w = 0; w < map_words; ++w) {
+                    r[1 + w / 4] |= run << (8 * (w % 4));
+                    run += (uint32_t)__builtin_popcount(m[w]);
+                }
+            }
     MBR_TRY(t.table.alloc(words * 4));
     MBR_HIP(hipMemcpy(t.table.p, rec.data(), words * 4, hipMemcpyHostToDevice));
     uint64_t lw = 0;
@@ -214,13 +218,19 @@ mbr_status launch_bt(const mbr_ranker *r, const void *q, uint64_t n, uint32_t *o
     a.lds_levels = t.lds_levels;
     a.lds_words = (uint32_t)t.lds_words;
     for (int l = 0; l < t.H; ++l) {
-        a.rw[l] = t.rw[l];
         a.off[l] = (uint32_t)t.off[l];
         a.shift[l] = (uint32_t)t.shift[l];
         a.cmask[l] = (1u << t.w[l]) - 1u;
     }
     const unsigned grid = mbr::grid_for(n, kBlock * kQ, mbr::device_cu_count() * 8);
-    bt_rank_kernel<P><<<grid, kBlock, (size_t)t.lds_words * 4, s>>>(static_cast<const P *>(q), n, out, a);
+    const size_t lds = (size_t)t.lds_words * 4;
+    const P *qp = static_cast<const P *>(q);
+    switch (t.rw[0]) {
+    case 2: bt_rank_kernel<P, 2><<<grid, kBlock, lds, s>>>(qp, n, out, a); break;
+    case 4: bt_rank_kernel<P, 4><<<grid, kBlock, lds, s>>>(qp, n, out, a); break;
+    case 8: bt_rank_kernel<P, 8><<<grid, kBlock, lds, s>>>(qp, n, out, a); break;
+    default: bt_rank_kernel<P, 16><<<grid, kBlock, lds, s>>>(qp, n, out, a); break;
+    }
     MBR_HIP(hipGetLastError());
     return MBR_OK;
 }

@@ -55,6 +55,7 @@ struct mbr_hubbard {
     std::vector<mbr_ranker *> ttries;
     DevBuf d_trie;                      // HvTrieDesc per sector
     uint32_t trie_lds = 0;              // LDS entries the largest staged top levels need
+    int32_t trie_k = 0;                 // chunk width of the tries
     ~mbr_hubbard() {
         for (auto *r : ttries) mbr_ranker_destroy(r);
         for (auto *s : tsecs) mbr_sector_destroy(s);
@@ -1793,6 +1794,67 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     return MBR_OK;
 }
 
+// Trie-ranked product: each sector's list (built once) and a packed trie of
+// chunk width kt over it, replacing any earlier tries.
+mbr_status build_hv_tries(mbr_hubbard *h, int kt, void *stream) {
+    hipStream_t s = as_stream(stream);
+    const int L = h->L;
+    if (kt < 4 || kt > 16) MBR_FAIL(MBR_EINVAL, "trie chunk width k=%d outside 4..16", kt);
+    if ((2 * L + kt - 1) / kt > 8) MBR_FAIL(MBR_EUNSUPPORTED, "trie of %d levels (at most 8)", (2 * L + kt - 1) / kt);
+    const uint64_t lo = (1ull << L) - 1;
+    if (h->tsecs.empty())
+        for (auto &sc : h->secs) {
+            const mbr_popc_cons cons[3] = {{(lo << L) | lo, sc.n_up + sc.n_dn, sc.n_up + sc.n_dn},
+                                           {lo, sc.n_dn, sc.n_dn},
+                                           {lo << L, sc.n_up, sc.n_up}};
+            mbr_sector *sec = nullptr;
+            MBR_TRY(mbr_sector_build(2 * L, 32, 3, cons, &sec, stream));
+            h->tsecs.push_back(sec);
+        }
+    std::vector<mbr_ranker *> tries;
+    auto drop = [&]() {
+        for (auto *r : tries) mbr_ranker_destroy(r);
+    };
+    std::vector<HvTrieDesc> td;
+    uint32_t lds = 0;
+    for (mbr_sector *sec : h->tsecs) {
+        mbr_ranker *tr = nullptr;
+        mbr_status st = mbr_build_trie(sec, kt, &tr, stream);
+        if (st != MBR_OK) {
+            drop();
+            return st;
+        }
+        tries.push_back(tr);
+        const TrieLevels &t = *tr->trie;
+        HvTrieDesc dd{};
+        dd.tab = t.table.as<uint32_t>();
+        dd.states = sec->states.as<uint32_t>();
+        dd.H = (uint32_t)t.H;
+        dd.lds_levels = (uint32_t)t.lds_levels;
+        dd.lds_entries = (uint32_t)t.lds_entries;
+        for (int l = 0; l < t.H; ++l) {
+            dd.wmask[l] = (uint32_t)((1ull << t.w[l]) - 1);
+            dd.shift[l] = t.shift[l];
+            dd.off[l] = t.off[l];
+        }
+        dd.off[t.H] = t.off[t.H];
+        lds = std::max(lds, dd.lds_entries);
+        td.push_back(dd);
+    }
+    DevBuf d;
+    mbr_status st = upload(d, td.data(), td.size() * sizeof(HvTrieDesc), s);
+    if (st != MBR_OK) {
+        drop();
+        return st;
+    }
+    for (auto *r : h->ttries) mbr_ranker_destroy(r);
+    h->ttries = std::move(tries);
+    h->d_trie = std::move(d);
+    h->trie_lds = (lds + 3) & ~3u;  // the partial sums after it stay 16-byte aligned
+    h->trie_k = kt;
+    return configure(h, (L + 1) / 2, -1, 512, s);
+}
+
 std::string tune_key(const mbr_hubbard *h) {
     hipDeviceProp_t p{};
     (void)hipGetDeviceProperties(&p, h->device);
@@ -1805,6 +1867,72 @@ std::string tune_key(const mbr_hubbard *h) {
     for (auto &c : key)
         if (c == ' ' || c == '\t' || c == '\n') c = '_';
     return key;
+}
+
+// Trie-ranked product: time the chunk widths that give two, three and four
+// levels over the 2L-bit patterns (at least 4 bits, at most 16) and keep the
+// fastest; same cache file and format as the launch-shape tuner, under the
+// key with ";trie" appended (the k field holds the trie's width).
+mbr_status autotune_trie_k(mbr_hubbard *h, int32_t reps, void *stream) {
+    hipStream_t s = as_stream(stream);
+    const int M = 2 * h->L;
+    const std::string key = tune_key(h) + ";trie";
+    const char *path = std::getenv("MBR_AUTOTUNE_CACHE");
+    if (path && *path) {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k0;
+            int kk = 0, gg = 0, bb = 0;
+            double ms = 0;
+            if (!(ls >> k0 >> kk >> gg >> bb >> ms) || k0 != key) continue;
+            if (kk == h->trie_k || build_hv_tries(h, kk, stream) == MBR_OK) {
+                h->tuned_ms = ms;
+                return MBR_OK;
+            }
+        }
+        clear_error();
+    }
+    std::vector<int> ks;
+    for (int levels = 2; levels <= 4; ++levels) ks.push_back(std::min(16, std::max(4, (M + levels - 1) / levels)));
+    std::sort(ks.begin(), ks.end());
+    ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+    const size_t tsz = h->precision == MBR_F64 ? 8 : 4;
+    DevBuf bx, by;
+    MBR_TRY(bx.alloc(h->total * tsz));
+    MBR_TRY(by.alloc(h->total * tsz));
+    MBR_HIP(hipMemsetAsync(bx.p, 0, h->total * tsz, s));
+    hipEvent_t e0, e1;
+    MBR_HIP(hipEventCreate(&e0));
+    MBR_HIP(hipEventCreate(&e1));
+    int bk = h->trie_k;
+    double best = 1e30;
+    for (int k : ks) {
+        if (k != h->trie_k && build_hv_tries(h, k, stream) != MBR_OK) continue;
+        HvEpilogue ep{};
+        if (hubbard_launch(h, bx.p, by.p, ep, s) != MBR_OK) continue;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) (void)hubbard_launch(h, bx.p, by.p, ep, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms / reps < best) {
+            best = ms / reps;
+            bk = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    clear_error();
+    if (bk != h->trie_k) MBR_TRY(build_hv_tries(h, bk, stream));
+    h->tuned_ms = best < 1e30 ? best : 0.0;
+    if (path && *path && best < 1e30) {
+        std::ofstream outf(path, std::ios::app);
+        if (outf) outf << key << " " << bk << " " << -1 << " " << 512 << " " << best << "\n";
+    }
+    return MBR_OK;
 }
 
 }  // namespace
@@ -1876,39 +2004,7 @@ mbr_status mbr_hubbard_create(const mbr_hubbard_desc *d, mbr_hubbard **out, void
     if (h->rank_kind == MBR_HV_RANK_TRIE) {
         // each sector's ascending list of 2L-bit patterns and a packed trie on
         // it; chunk width k (0: four levels)
-        const int kt = d->k > 0 ? d->k : std::max(4, (2 * L + 3) / 4);
-        std::vector<HvTrieDesc> td;
-        const uint64_t lo = (1ull << L) - 1;
-        for (auto &sc : h->secs) {
-            const mbr_popc_cons cons[3] = {{(lo << L) | lo, sc.n_up + sc.n_dn, sc.n_up + sc.n_dn},
-                                           {lo, sc.n_dn, sc.n_dn},
-                                           {lo << L, sc.n_up, sc.n_up}};
-            mbr_sector *sec = nullptr;
-            MBR_TRY(mbr_sector_build(2 * L, 32, 3, cons, &sec, stream));
-            h->tsecs.push_back(sec);
-            mbr_ranker *tr = nullptr;
-            MBR_TRY(mbr_build_trie(sec, kt, &tr, stream));
-            h->ttries.push_back(tr);
-            const TrieLevels &t = *tr->trie;
-            if (t.H > 8) MBR_FAIL(MBR_EUNSUPPORTED, "trie of %d levels (at most 8)", t.H);
-            HvTrieDesc dd{};
-            dd.tab = t.table.as<uint32_t>();
-            dd.states = sec->states.as<uint32_t>();
-            dd.H = (uint32_t)t.H;
-            dd.lds_levels = (uint32_t)t.lds_levels;
-            dd.lds_entries = (uint32_t)t.lds_entries;
-            for (int l = 0; l < t.H; ++l) {
-                dd.wmask[l] = (uint32_t)((1ull << t.w[l]) - 1);
-                dd.shift[l] = t.shift[l];
-                dd.off[l] = t.off[l];
-            }
-            dd.off[t.H] = t.off[t.H];
-            h->trie_lds = std::max(h->trie_lds, dd.lds_entries);
-            td.push_back(dd);
-        }
-        h->trie_lds = (h->trie_lds + 3) & ~3u;  // the partial sums after it stay 16-byte aligned
-        MBR_TRY(upload(h->d_trie, td.data(), td.size() * sizeof(HvTrieDesc), s));
-        MBR_TRY(configure(h.get(), (L + 1) / 2, -1, 512, s));
+        MBR_TRY(build_hv_tries(h.get(), d->k > 0 ? d->k : std::max(4, (2 * L + 3) / 4), stream));
         *out = h.release();
         return MBR_OK;
     }
@@ -1946,7 +2042,7 @@ mbr_status mbr_hubbard_destroy(mbr_hubbard *h) {
 
 mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg) {
     if (!h || !cfg) MBR_FAIL(MBR_EINVAL, "null argument");
-    cfg->k = h->k;
+    cfg->k = h->rank_kind == MBR_HV_RANK_TRIE ? h->trie_k : h->k;
     cfg->G = h->G;
     cfg->block = h->block;
     cfg->tiles = (int32_t)h->tiles_by_slot.size();
@@ -1971,7 +2067,7 @@ mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t 
 mbr_status mbr_hubbard_autotune(mbr_hubbard *h, int32_t reps, void *stream) {
     if (!h) MBR_FAIL(MBR_EINVAL, "null handle");
     if (reps < 1 || reps > 1000) MBR_FAIL(MBR_EINVAL, "reps=%d", reps);
-    if (h->rank_kind == MBR_HV_RANK_TRIE) MBR_FAIL(MBR_EUNSUPPORTED, "a trie-ranked product has one launch shape");
+    if (h->rank_kind == MBR_HV_RANK_TRIE) return autotune_trie_k(h, reps, stream);
     hipStream_t s = as_stream(stream);
     const std::string key = tune_key(h);
     const char *path = std::getenv("MBR_AUTOTUNE_CACHE");

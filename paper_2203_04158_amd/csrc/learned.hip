@@ -915,6 +915,54 @@ mbr_status mbr_learned_max_error(const mbr_ranker *r, uint64_t *e, int32_t *uses
     return MBR_OK;
 }
 
+mbr_status mbr_learned_autotune(mbr_ranker *r, const void *d_q, uint64_t n, int32_t reps, double *ms_window,
+                                double *ms_fallback, void *stream) {
+    using namespace mbr;
+    if (!r || r->kind != MBR_RANKER_LEARNED || !r->learned) MBR_FAIL(MBR_EINVAL, "not a learned ranker");
+    if (!r->fallback) MBR_FAIL(MBR_EINVAL, "learned ranker without a fallback");
+    if (!d_q || n == 0) MBR_FAIL(MBR_EINVAL, "no queries");
+    if (reps < 1 || reps > 1000) MBR_FAIL(MBR_EINVAL, "reps=%d outside 1..1000", reps);
+    hipStream_t s = as_stream(stream);
+    LearnedModel &lm = *r->learned;
+    const int32_t keep = lm.uses_window;
+    DevBuf ranks;
+    MBR_TRY(ranks.alloc(n * 4));
+    hipEvent_t e0, e1;
+    MBR_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        MBR_FAIL(MBR_EHIP, "hipEventCreate failed");
+    }
+    double t[2] = {0, 0};
+    mbr_status st = MBR_OK;
+    for (int path = 0; path < 2 && st == MBR_OK; ++path) {
+        lm.uses_window = path == 0 ? 1 : 0;  // 0: window search, 1: fallback
+        st = rank_learned_launch(r, d_q, n, ranks.as<uint32_t>(), s);
+        if (st != MBR_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < reps && st == MBR_OK; ++i) st = rank_learned_launch(r, d_q, n, ranks.as<uint32_t>(), s);
+        (void)hipEventRecord(e1, s);
+        float ms = 0;
+        hipError_t he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (st == MBR_OK && he != hipSuccess) {
+            set_error("timing failed: %s", hipGetErrorString(he));
+            st = MBR_EHIP;
+        }
+        t[path] = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MBR_OK) {
+        lm.uses_window = keep;
+        return st;
+    }
+    lm.uses_window = t[0] <= t[1] ? 1 : 0;
+    if (ms_window) *ms_window = t[0];
+    if (ms_fallback) *ms_fallback = t[1];
+    return MBR_OK;
+}
+
 mbr_status mbr_learned_stats(const mbr_ranker *r, mbr_learned_info *info) {
     if (!r || r->kind != MBR_RANKER_LEARNED || !info) MBR_FAIL(MBR_EINVAL, "not a learned ranker");
     const LearnedModel &lm = *r->learned;

@@ -50,3 +50,14 @@ def test_sector_from_list_argument_errors_without_gpu():
     assert L.mbr_sector_from_list(12, 32, ctypes.c_void_p(16), 0xFFFFFFFF, ctypes.byref(h), None) == -6
     assert L.mbr_sector_from_list(12, 32, None, 0, None, None) == -1                # null handle
     assert L.mbr_status_str(-5) == b"state list has duplicates"
+
+
+def test_autotune_argument_errors_without_gpu():
+    L = mbr.lib()
+    h = ctypes.c_void_p()
+    res = mbr.RankTuning()
+    assert L.mbr_rank_autotune(None, 1, None, 0, None, 0, 1, ctypes.byref(res), ctypes.byref(h), None) == -1
+    assert b"null sector" in L.mbr_last_error()
+    assert L.mbr_rank_autotune(None, 1, None, 0, None, 0, 1, None, ctypes.byref(h), None) == -1
+    assert L.mbr_learned_autotune(None, None, 0, 1, None, None, None) == -1
+    assert b"not a learned ranker" in L.mbr_last_error()

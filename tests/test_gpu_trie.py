@@ -134,7 +134,11 @@ def _bt_check(M, cons, k, width=32, n_noise=20000, seed=1):
         above -= widths[l]                        # bits below and in chunk l
         pre = st >> np.uint64(above + widths[l]) if above + widths[l] < 64 else np.zeros_like(st)
         assert recs[l] == np.unique(pre).size, (l, recs[l])
-        assert rbytes[l] == max(8, 1 << int(np.ceil(np.log2(4 + (1 << widths[l]) / 8))))
+        # one record size on every level, for the widest chunk: base, prefix
+        # bytes of the map words (when there are several), the map; a power of two
+        mw = -(-(1 << max(widths)) // 32)
+        need = 4 * (1 + (-(-mw // 4) if mw > 1 else 0) + mw)
+        assert rbytes[l] == max(8, 1 << int(np.ceil(np.log2(need))))
     dev = dev_u32 if width == 32 else dev_u64
     got = host_rank(mbr.rank_batch(r, dev(st)))
     assert np.array_equal(got, np.arange(st.size))
