@@ -752,7 +752,7 @@ def main():
                                 U=[g["U"]] + [0.0] * (Ls - 1), eps=[g["eps_d"]] + g["eps_bath"], precision=mbr.F32)
         if args.G is not None:
             cfg = mbr.hubbard_get_config(ha)
-            mbr.hubbard_set_config(ha, k=cfg["k"], G=args.G, block=args.block)
+            mbr.hubbard_set_config(ha, k=args.k or cfg["k"], G=args.G, block=args.block)
         x = torch.from_numpy(synth.start_vector(5, ha.dim)).to(device=dev, dtype=torch.float32)
         y = torch.empty_like(x)
         for _ in range(args.kernel_reps):

@@ -500,7 +500,9 @@ constexpr int kRowsMaxR = 4;          // alpha_dn per lane
 constexpr int kUpMax = 8;             // up-hop gathers in flight per row (more run in a tail loop)
 constexpr int kRowsDownFixed = 12;    // down-hop entries summed without a branch (padding adds zeros)
 constexpr uint32_t kRowsMaxX = 4096;  // staged elements per tile (blocks of C_dn + 1): offsets fit 16 bits
-constexpr uint32_t kRowsSlots = 3;    // fp32: alpha_up blocks per tile when each takes a row slot (512 < C_dn <= 1024)
+constexpr uint32_t kRowsSlots = 4;    // fp32: alpha_up blocks per tile when each takes a row slot (512 < C_dn <= 1024)
+constexpr uint32_t kRowsSlotsUT = 3;  // the same with uniform hopping (R = 4 would spill there)
+__host__ __device__ constexpr uint32_t rows_slots(bool ut) { return ut ? kRowsSlotsUT : kRowsSlots; }
 static_assert(kRowsMaxX <= (uint32_t)(kRowsMaxR * kRowsBlock), "R slots cover a block");
 
 // LDS layout: rank table | bond amplitudes | on-site U | reduction scratch |
@@ -655,12 +657,21 @@ __device__ __forceinline__ void rows_uplists(const HvArgs &a, const uint16_t *rt
     const int lane = threadIdx.x & 63;
     const unsigned long long grp = 0xFFFFull << (lane & 48);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t nu = (uint32_t)__popcll(bal & grp);
     if (hop) {
         const uint32_t pos = (uint32_t)__popcll(bal & grp & below);
         ut[g * kRowsNB + pos] = tgt;
         uc[g * kRowsNB + pos] = coef;
     }
-    if (b == 0 && g < nblk) un[g] = (uint32_t)__popcll(bal & grp);
+    if (g < nblk && b >= nu) {
+        // entries past the hops (every position b >= nu, written by lane b
+        // whether or not it hops itself: a hop lane's own entry lies below nu):
+        // block 0 of the sector with coefficient 0, so a fixed number of
+        // gathers can be read and summed without a branch
+        ut[g * kRowsNB + b] = 0u;
+        uc[g * kRowsNB + b] = (T)0;
+    }
+    if (b == 0 && g < nblk) un[g] = nu;
 }
 
 // Staging of a tile's x rows: each lane loads kRowsPre rows into registers
@@ -685,14 +696,23 @@ __device__ __forceinline__ void rows_pre_store(unsigned char *bb, size_t cs, uin
     T *xp = reinterpret_cast<T *>(bb);
     T *xm = reinterpret_cast<T *>(bb + cs);
     const uint32_t rows = nblk * cdn;
+    // block g = e / C_dn of element e = t + j 1024, stepped from j to j + 1
+    // by the quotient and remainder of 1024 / C_dn
+    const uint32_t qs = (uint32_t)kRowsBlock / cdn, rs = (uint32_t)kRowsBlock - qs * cdn;
+    uint32_t g = threadIdx.x / cdn, rem = threadIdx.x - g * cdn;
 #pragma unroll
     for (int j = 0; j < kRowsPre; ++j) {
         const uint32_t e = threadIdx.x + j * kRowsBlock;
         if (e < rows) {
-            const uint32_t g = e / cdn;
             const uint32_t pos = e + g;  // g (C_dn + 1) + (e - g C_dn)
             xp[pos] = pre[j];
             xm[pos] = -pre[j];
+        }
+        g += qs;
+        rem += rs;
+        if (rem >= cdn) {
+            rem -= cdn;
+            ++g;
         }
     }
     if (threadIdx.x < nblk) xp[threadIdx.x * (cdn + 1) + cdn] = (T)0;
@@ -778,6 +798,35 @@ __device__ __forceinline__ RowsTile rows_desc_uniform(const uint4 (&q)[2]) {
     r.sector = w2 >> 16;
     r.slot = u(q[1].w);
     return r;
+}
+
+// Up-hop terms kUpMax .. of one row past the first batch, in groups of four:
+// a group's gathers are all issued before its sums (entries past the block's
+// hops are block 0 with coefficient 0, so a group needs no branch inside).
+// U: the lists are the same for the whole wave (values taken from lane 0);
+// otherwise a group runs when any lane of the wave needs it.
+template <class T, bool U>
+__device__ __forceinline__ T rows_up_tail(const T *xsec, const uint32_t *utb, const T *ucb, uint32_t cdn,
+                                          uint32_t rd, uint32_t nu, T v) {
+#pragma unroll
+    for (int h0 = kUpMax; h0 < kRowsNB; h0 += 4) {
+        const bool need = U ? nu > (uint32_t)h0 : __ballot(nu > (uint32_t)h0) != 0;
+        if (!need) break;
+        T g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t t = utb[h0 + q];
+            if constexpr (U) t = __builtin_amdgcn_readfirstlane(t);
+            g[q] = xsec[(uint64_t)t * cdn + rd];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T c = ucb[h0 + q];
+            if constexpr (U) c = uniform_val(c);
+            v = fma_t(c, g[q], v);
+        }
+    }
+    return v;
 }
 
 template <class T, bool LZ, int R, bool UT>
@@ -906,11 +955,11 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 const T eu = uniform_val(ue[0]);
                 const T *src[kUpMax];
                 T cf[kUpMax];
+                // entries past nu are block 0 with coefficient 0: read without a branch
 #pragma unroll
                 for (int h = 0; h < kUpMax; ++h) {
-                    const bool hh = h < (int)nu;
-                    src[h] = xsec + (uint64_t)(hh ? __builtin_amdgcn_readfirstlane(ut[h]) : 0u) * cdn;
-                    cf[h] = hh ? uniform_val(uc[h]) : (T)0;
+                    src[h] = xsec + (uint64_t)__builtin_amdgcn_readfirstlane(ut[h]) * cdn;
+                    cf[h] = uniform_val(uc[h]);
                 }
                 T gx[2][kUpMax], gp_[2], ge[2];
                 uint32_t ga[2];
@@ -962,9 +1011,7 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                         // cf = 0 and gx = x[row 0] past nu: those terms add an exact zero
 #pragma unroll
                         for (int h = 0; h < kUpMax; ++h) v = fma_t(cf[h], gx[s][h], v);
-                        for (uint32_t h = kUpMax; h < nu; ++h)
-                            v = fma_t(uniform_val(uc[h]),
-                                      xsec[(uint64_t)__builtin_amdgcn_readfirstlane(ut[h]) * cdn + rd], v);
+                        v = rows_up_tail<T, true>(xsec, ut, uc, cdn, (uint32_t)rd, nu, v);
                         const uint64_t row = base + rd;
                         if constexpr (LZ) {
                             const T uu = lz_out(v, c1, c2, gp_[s], has_p);
@@ -975,7 +1022,7 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                         }
                     }
                 }
-            } else if (sizeof(T) == 4 && R <= (int)kRowsSlots && c.gp == 0) {
+            } else if (sizeof(T) == 4 && R <= (int)rows_slots(UT) && c.gp == 0) {
                 // Several alpha_up blocks per tile (C_dn <= 1024), one per row
                 // slot: lane tid owns alpha_dn = tid in every block, so its
                 // down-hop list, half state and energy serve all of them, and
@@ -1010,13 +1057,12 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                 const T ged = kKeepHs ? gec[0] : ge1;
                 const int nblk = (int)c.nblk;
                 auto gather = [&](int g, int sl) {
-                    const uint32_t nu = __builtin_amdgcn_readfirstlane(un[g]);
+                    // entries past the block's hops are block 0 with coefficient 0
 #pragma unroll
                     for (int h = 0; h < kUpMax; ++h) {
-                        const bool hh = h < (int)nu;
-                        const uint32_t t = hh ? __builtin_amdgcn_readfirstlane(ut[g * kRowsNB + h]) : 0u;
+                        const uint32_t t = __builtin_amdgcn_readfirstlane(ut[g * kRowsNB + h]);
                         gx[sl][h] = xsec[(uint64_t)t * cdn + rc];
-                        cfs[sl][h] = hh ? uniform_val(uc[g * kRowsNB + h]) : (T)0;
+                        cfs[sl][h] = uniform_val(uc[g * kRowsNB + h]);
                     }
                     if constexpr (LZ) gp_[sl] = pp[base + (uint64_t)g * cdn + rc];
                 };
@@ -1037,10 +1083,8 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                         T v = fma_t(dg, xv, UT ? tu * acc : acc);
 #pragma unroll
                         for (int h = 0; h < kUpMax; ++h) v = fma_t(cfs[sl][h], gx[sl][h], v);
-                        for (uint32_t h = kUpMax; h < nu; ++h)
-                            v = fma_t(uniform_val(uc[r * kRowsNB + h]),
-                                      xsec[(uint64_t)__builtin_amdgcn_readfirstlane(ut[r * kRowsNB + h]) * cdn + rd],
-                                      v);
+                        v = rows_up_tail<T, true>(xsec, ut + r * kRowsNB, uc + r * kRowsNB, cdn, (uint32_t)rd,
+                                                  nu, v);
                         const uint64_t row = base + (uint64_t)r * cdn + rd;
                         if constexpr (LZ) {
                             const T uu = lz_out(v, c1, c2, gp_[sl], has_p);
@@ -1059,10 +1103,10 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                     const int rd = tid - g * (int)cdn;
                     const uint64_t row = base + (uint64_t)g * cdn + rd;
                     const uint32_t nu = un[g];
+                    // entries past nu are block 0 with coefficient 0: no branch
                     T gx[kUpMax];
 #pragma unroll
-                    for (int h = 0; h < kUpMax; ++h)
-                        gx[h] = h < (int)nu ? xsec[(uint64_t)ut[g * kRowsNB + h] * cdn + rd] : (T)0;
+                    for (int h = 0; h < kUpMax; ++h) gx[h] = xsec[(uint64_t)ut[g * kRowsNB + h] * cdn + rd];
                     uint32_t hl[kWords];
                     rows_load_list(slists + (size_t)rd * kWords, hl);
                     const T pv = has_p ? p[row] : (T)0;
@@ -1074,10 +1118,8 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
                     const T dg = ue[g] + edr + rows_u_energy<T>(ua[g] & adr, a, ul);
                     T v = fma_t(dg, xv, UT ? tu * acc : acc);
 #pragma unroll
-                    for (int h = 0; h < kUpMax; ++h)
-                        if (h < (int)nu) v = fma_t(uc[g * kRowsNB + h], gx[h], v);
-                    for (uint32_t h = kUpMax; h < nu; ++h)
-                        v = fma_t(uc[g * kRowsNB + h], xsec[(uint64_t)ut[g * kRowsNB + h] * cdn + rd], v);
+                    for (int h = 0; h < kUpMax; ++h) v = fma_t(uc[g * kRowsNB + h], gx[h], v);
+                    v = rows_up_tail<T, false>(xsec, ut + g * kRowsNB, uc + g * kRowsNB, cdn, (uint32_t)rd, nu, v);
                     if constexpr (LZ) {
                         const T uu = lz_out(v, c1, c2, pv, has_p);
                         out[row] = uu;
@@ -1627,6 +1669,8 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0, rows_gmax = 1, lrows = 0;
     std::vector<uint32_t> lists_ndn, lists_rows;
     int rows_R = 1;
+    bool t_uniform = true;  // every bond has one amplitude (the rows kernel's uniform-hopping instances)
+    for (auto &b : h->bonds) t_uniform = t_uniform && b.t == h->bonds[0].t;
     const uint32_t nbm = (uint32_t)std::max(1, h->nb);
     for (size_t si = 0; si < h->secs.size(); ++si) {
         HvSector sc{};
@@ -1651,10 +1695,10 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
                 sc.R = 1;
                 nblk = sc.gp;
             } else if (sc.cdn <= (uint32_t)kRowsBlock && tsz == 4) {
-                // one block per row slot (gp = 0): kRowsSlots blocks a tile
+                // one block per row slot (gp = 0): rows_slots() blocks a tile
                 // (fp32; in fp64 the extra slots would not fit the registers)
                 sc.gp = 0;
-                nblk = std::min<uint32_t>(kRowsSlots, kRowsMaxX / (sc.cdn + 1));
+                nblk = std::min<uint32_t>(rows_slots(t_uniform), kRowsMaxX / (sc.cdn + 1));
                 sc.R = nblk;
             } else {
                 // one block per tile, spread over ceil(C_dn / 1024) row slots
@@ -1723,8 +1767,6 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     const std::vector<uint32_t> fr = balanced_ranges(flat_tiles, hsec, kXcd);
     const size_t rows_lds = rows_lds_layout((uint32_t)((uint64_t)tab.nrows << k), rows_xcap, rows_gmax, tsz).total;
     if (!rows_tiles.empty() && rows_lds > kLdsMax) MBR_FAIL(MBR_EUNSUPPORTED, "rows kernel needs %zu bytes of LDS", rows_lds);
-    bool t_uniform = true;
-    for (auto &b : h->bonds) t_uniform = t_uniform && b.t == h->bonds[0].t;
     // commit
     h->tab = std::move(tab);
     h->k = k;
