@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <type_traits>
 
 #include "hubbard.hpp"
 
@@ -119,6 +120,67 @@ __global__ void lz_beta(const HvSector *secs, LzDev d, int m, double tol, int re
     }
 }
 
+// w = u - c q over elements [base, base + rows) of u (in place), returning
+// this lane's share of |w|^2.  The bulk goes in 16-byte packs, four per lane
+// in flight; the unaligned head and the tail element by element.  Both update
+// kernels use it, so their partials agree bit for bit.
+template <class T>
+__device__ __forceinline__ double tile_axpy_norm(T *__restrict__ u, const T *__restrict__ q, T c, uint64_t base,
+                                                 uint32_t rows) {
+    constexpr uint32_t V = 16 / sizeof(T);
+    using P = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    double acc = 0;
+    uint32_t head = (uint32_t)((V - base % V) % V);
+    if (head > rows) head = rows;
+    for (uint32_t e = threadIdx.x; e < head; e += blockDim.x) {
+        const T w = u[base + e] - c * q[base + e];
+        u[base + e] = w;
+        acc += (double)w * (double)w;
+    }
+    const uint32_t np = (rows - head) / V;
+    P *up = reinterpret_cast<P *>(u + base + head);
+    const P *qp = reinterpret_cast<const P *>(q + base + head);
+    constexpr int kU = 4;
+    uint32_t pk = threadIdx.x;
+    for (; pk + (kU - 1) * blockDim.x < np; pk += kU * blockDim.x) {
+        P a[kU], b[kU];
+#pragma unroll
+        for (int i = 0; i < kU; ++i) {
+            a[i] = up[pk + i * blockDim.x];
+            b[i] = qp[pk + i * blockDim.x];
+        }
+#pragma unroll
+        for (int i = 0; i < kU; ++i) {
+            T *av = reinterpret_cast<T *>(&a[i]);
+            const T *bv = reinterpret_cast<const T *>(&b[i]);
+#pragma unroll
+            for (uint32_t v = 0; v < V; ++v) {
+                av[v] = av[v] - c * bv[v];
+                acc += (double)av[v] * (double)av[v];
+            }
+            up[pk + i * blockDim.x] = a[i];
+        }
+    }
+    for (; pk < np; pk += blockDim.x) {
+        P a = up[pk];
+        const P b = qp[pk];
+        T *av = reinterpret_cast<T *>(&a);
+        const T *bv = reinterpret_cast<const T *>(&b);
+#pragma unroll
+        for (uint32_t v = 0; v < V; ++v) {
+            av[v] = av[v] - c * bv[v];
+            acc += (double)av[v] * (double)av[v];
+        }
+        up[pk] = a;
+    }
+    for (uint32_t e = head + np * V + threadIdx.x; e < rows; e += blockDim.x) {
+        const T w = u[base + e] - c * q[base + e];
+        u[base + e] = w;
+        acc += (double)w * (double)w;
+    }
+    return acc;
+}
+
 // w = u - c3 q over a tile's rows (in place in u); partial |w|^2.
 template <class T>
 __global__ void __launch_bounds__(kBlock) lz_update(const HvTile *tiles, uint32_t n_tiles,
@@ -135,12 +197,7 @@ __global__ void __launch_bounds__(kBlock) lz_update(const HvTile *tiles, uint32_
         const T c = (T)d.c3[tl.sector];
         const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
         const uint32_t rows = tl.nblk * sc.cdn;
-        double acc = 0;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
-            T w = u[base + e] - c * q[base + e];
-            u[base + e] = w;
-            acc += (double)w * (double)w;
-        }
+        const double acc = tile_axpy_norm(u, q, c, base, rows);
         double s = block_sum(acc, red);
         if (threadIdx.x == 0) d.pn[tl.slot] = s;
     }
@@ -178,12 +235,7 @@ __global__ void __launch_bounds__(kBlock) lz_alpha_update(const HvTile *tiles, u
         const HvSector sc = secs[tl.sector];
         const uint64_t base = sc.off + (uint64_t)tl.rup0 * sc.cdn;
         const uint32_t rows = tl.nblk * sc.cdn;
-        double acc = 0;
-        for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) {
-            T w = u[base + e] - c * q[base + e];
-            u[base + e] = w;
-            acc += (double)w * (double)w;
-        }
+        const double acc = tile_axpy_norm(u, q, c, base, rows);
         double bs = block_sum(acc, red);
         if (threadIdx.x == 0) d.pn[tl.slot] = bs;
     }
