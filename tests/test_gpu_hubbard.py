@@ -425,6 +425,38 @@ def test_anderson_flat_and_rows_kernels_bitwise_equal_fp32(G):
     assert torch.equal(ys[0], ys[1])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_l10_every_row_and_launch_shapes(prec):
+    """A periodic L=10 chain with uniform hopping (C_dn up to 252: several
+    alpha_up blocks per rows-kernel tile; sectors with a single spin-down or
+    spin-up configuration and with no hops at all included): every row against
+    the oracle, and the rows, flat and tile kernels bitwise equal."""
+    L, U = 10, 3.5
+    bonds = OH.chain_bonds(L, periodic=True)
+    sectors = [(5, 5), (4, 6), (3, 2), (0, 10), (10, 1)]
+    h = mbr.hubbard_create(L, bonds, sectors, U=[U] * L, precision=prec)
+    cfg = mbr.hubbard_get_config(h)
+    x = 2 * synth.uniform01(31, h.dim) - 1
+    if prec == mbr.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x, prec)
+    ys = []
+    for G, block in ((0, 512), (-1, 512), (2, 256)):
+        mbr.hubbard_set_config(h, cfg["k"], G, block)
+        y = torch.empty_like(xd)
+        mbr.hubbard_apply(h, xd, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
+    y = ys[0].cpu().numpy().astype(np.float64)
+    tl = OH.terms(L, bonds, U)
+    eps_p = EPS64 if prec == mbr.F64 else EPS32
+    for si, (nu, nd) in enumerate(sectors):
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        want, ab = _oracle_apply_all(OH.sector(L, nu, nd), tl, x[o0:o1])
+        bad = np.abs(y[o0:o1] - want) > 64 * eps_p * ab + 1e-300
+        assert not bad.any(), (nu, nd, np.nonzero(bad)[0][:5])
+
+
 @pytest.mark.parametrize("L,sectors,prec", [(6, [(3, 3), (2, 4), (0, 3), (6, 6)], 0),
                                             (8, [(4, 4), (3, 5)], 1)])
 def test_trie_ranked_product_bitwise_equals_halves(L, sectors, prec):
