@@ -9,7 +9,7 @@ import pytest
 from oracle import combinatorics as OC
 from oracle import hamiltonian as OH
 import synth
-from tests._util import dev_u32, host_rank, say
+from tests._util import dev_u32, dev_u64, host_rank, say
 
 pytestmark = pytest.mark.gpu
 mbr = pytest.importorskip("paper_2203_04158_amd")
@@ -48,6 +48,24 @@ def test_rank_autotune_picks_a_candidate_and_ranks_exactly(kind, ks, tmp_path, m
     assert t2["from_cache"] and t2["k"] == t["k"] and t2["tried"] == 0
     assert np.array_equal(host_rank(mbr.rank_batch(r2, qd)), want)
     assert len(cache.read_text().splitlines()) == 3
+
+
+@pytest.mark.parametrize("kind", [1, 3, 8])
+def test_rank_autotune_64_bit_patterns(kind):
+    """M = 40 with 64-bit patterns (three particles, one or two of them in
+    orbitals 0-3 for the tries, three anywhere for the staggered tables):
+    whatever width is picked, the ranks equal the oracle's bisection."""
+    M = 40
+    cons = OC.constraints(M, 3) if kind == 1 else OC.constraints(M, 3, [(0xF, 1, 2)])
+    st = OC.sector_enumerate(M, cons)
+    s = mbr.sector_build(M, cons, width_bits=64)
+    noise = synth.splitmix64(91, 20000) & np.uint64((1 << M) - 1)
+    q = np.concatenate([st[synth.uniform_indices(92, 30000, st.size)], noise])
+    qd = dev_u64(q)
+    r, t = mbr.rank_autotune(s, kind, qd, ks=[4, 6, 8], reps=2)
+    say("rank autotune, 64-bit patterns, kind", kind, t)
+    assert t["k"] in (4, 6, 8) and t["tried"] == 3
+    assert np.array_equal(host_rank(mbr.rank_batch(r, qd)), OC.bisect_rank(st, q))
 
 
 def test_rank_autotune_rejects():
