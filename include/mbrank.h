@@ -227,6 +227,11 @@ mbr_status mbr_build_bisect_ranker(const mbr_sector *s, mbr_ranker **out);
 mbr_status mbr_build_cns_ranker(int32_t M, int32_t N, int32_t width_bits, mbr_ranker **out,
                                 void *stream);
 
+/* Device bytes of a packed or bitmap trie (all levels, padding included):
+ * the memory overhead of Sec. IV is f = bytes / (4 N_s).  EINVAL for other
+ * rankers. */
+mbr_status mbr_trie_bytes(const mbr_ranker *r, uint64_t *bytes);
+
 /* Layout of a trie ranker: *levels = number of levels (chunks), *lds_levels =
  * how many top levels each workgroup stages in LDS, entries[l] = uint32
  * entries of level l (padding included) for l < min(levels, cap). */

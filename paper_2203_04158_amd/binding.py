@@ -140,6 +140,7 @@ _SIGS = {
     "mbr_build_sampled_ranker": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p]),
     "mbr_build_cns_ranker": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
                                          C.c_void_p]),
+    "mbr_trie_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "mbr_trie_level_entries": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                            C.POINTER(C.c_int32)]),
     "mbr_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -387,6 +388,13 @@ def build_bitmap_trie(sector: Sector, k: int, stream=None) -> Ranker:
     h = C.c_void_p()
     _check("mbr_build_bitmap_trie", lib().mbr_build_bitmap_trie(sector.handle, k, C.byref(h), _stream(stream)))
     return Ranker(h, keep=(sector,))
+
+
+def trie_bytes(ranker: Ranker) -> int:
+    """Device bytes of a packed or bitmap trie (f = bytes / (4 N_s))."""
+    b = C.c_uint64()
+    _check("mbr_trie_bytes", lib().mbr_trie_bytes(ranker.handle, C.byref(b)))
+    return int(b.value)
 
 
 def bitmap_trie_levels(ranker: Ranker):

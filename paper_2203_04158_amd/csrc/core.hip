@@ -101,6 +101,14 @@ const char *mbr_last_error(void) { return mbr::g_err.c_str(); }
 
 int32_t mbr_version(void) { return 10100; }
 
+mbr_status mbr_trie_bytes(const mbr_ranker *r, uint64_t *bytes) {
+    if (!r || !bytes) MBR_FAIL(MBR_EINVAL, "null ranker or output");
+    if (r->kind == MBR_RANKER_TRIE) *bytes = trie_bytes(r->trie);
+    else if (r->kind == MBR_RANKER_BITMAP_TRIE) *bytes = r->btrie ? r->btrie->table.bytes : 0;
+    else MBR_FAIL(MBR_EINVAL, "not a trie ranker (kind %d)", r->kind);
+    return MBR_OK;
+}
+
 mbr_status mbr_ranker_info_get(const mbr_ranker *r, mbr_ranker_info *info) {
     if (!r || !info) MBR_FAIL(MBR_EINVAL, "null ranker or info");
     mbr_ranker_info o{};

@@ -61,3 +61,5 @@ def test_autotune_argument_errors_without_gpu():
     assert L.mbr_rank_autotune(None, 1, None, 0, None, 0, 1, None, ctypes.byref(h), None) == -1
     assert L.mbr_learned_autotune(None, None, 0, 1, None, None, None) == -1
     assert b"not a learned ranker" in L.mbr_last_error()
+    assert L.mbr_trie_bytes(None, None) == -1
+    assert b"null ranker" in L.mbr_last_error()

@@ -33,6 +33,7 @@ def _check(M, cons, k, width=32, n_noise=20000, seed=1):
     assert info.levels == -(-M // k)
     ent, lds_lv = mbr.trie_level_entries(r)
     assert len(ent) == info.levels and 4 * sum(ent) == info.bytes and 0 <= lds_lv <= info.levels
+    assert mbr.trie_bytes(r) == info.bytes
     assert ent[0] == 1 << OT.chunk_widths(M, k, "last")[0]  # the root is a full node
     if M - OT.chunk_widths(M, k, "last")[-1] <= 26:  # range of the oracle's size counter
         assert info.bytes == 4 * _expected_entries(st, M, k)
@@ -128,6 +129,7 @@ def _bt_check(M, cons, k, width=32, n_noise=20000, seed=1):
     H = -(-M // k)
     assert info.kind == mbr.RANKER_BITMAP_TRIE and info.levels == H
     recs, rbytes, lds = mbr.bitmap_trie_levels(r)
+    assert mbr.trie_bytes(r) == info.bytes >= sum(n * b for n, b in zip(recs, rbytes))
     widths = [M - (H - 1) * k] + [k] * (H - 1)
     above = M
     for l in range(H):
