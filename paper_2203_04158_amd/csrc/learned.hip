@@ -21,14 +21,20 @@
 // Parameters (6337 fp32 masters): W1[64][32], b1[64], W2[64][64], b2[64],
 // w3[64], b3.  Queries use their bf16 roundings with fp32 accumulation.
 //
-// Inference runs on the matrix cores, v_mfma_f32_16x16x16bf16 (wave64): a wave
+// Inference runs on the matrix cores, v_mfma_f32_16x16x32_bf16 (wave64, the
+// gfx950 form with 32 products per lane pair and instruction): a wave
 // evaluates 16 queries per product chain.  Layers are computed transposed,
-// D = W * H^T (features x queries), because the 16x16 fp32 output fragment of
-// one layer (lane l holds features 4*(l/16)+r of query l%16) is exactly the
-// lane layout of the next product's B operand (K = features, N = queries);
-// activations go from fp32 to bf16 in registers, with no shuffles between
-// layers.  Training runs in fp32 on the vector ALUs (forward with the bf16
-// weights, backward, fixed-order batch reductions, Adam).
+// D = W * H^T (features x queries): the 16x16 fp32 output fragment of one
+// layer (lane l holds features 4*(l/16)+r of query l%16 of a 16-feature
+// tile) feeds the next product's B operand (K = features, N = queries)
+// without shuffles, because the order in which a product sums over K is
+// free: the K slot (g, j) of lane group g = l/16 and element j < 8 of a
+// 32-feature chunk c takes feature 16 (2c + j/4) + 4 g + j%4, i.e. the two
+// output fragments of tiles 2c and 2c+1 side by side, and the weights are
+// loaded in that order.  Activations go from fp32 to bf16 in registers
+// (rounded, then ReLU as a packed 16-bit integer maximum).  Training runs in
+// fp32 on the vector ALUs (forward with the bf16 weights, backward,
+// fixed-order batch reductions, Adam).
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -42,7 +48,9 @@ constexpr int P_W1 = 0, P_B1 = 2048, P_W2 = 2112, P_B2 = 6208, P_W3 = 6272, P_B3
 constexpr int kParams = 6337;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
 
 __host__ __device__ inline uint16_t f2bf(float f) {
     // round to nearest even (finite inputs)
@@ -62,13 +70,16 @@ __host__ __device__ inline float bf2f(uint16_t b) {
 // Per-lane weight fragments of the three products (A operands), biases in the
 // output-fragment layout.
 struct MlpFrags {
-    bf16x4 w1[4][2];
-    bf16x4 w2[4][4];
-    bf16x4 w3[4];
+    bf16x8 w1[4];     // tile t: one 32-input chunk
+    bf16x8 w2[4][2];  // tile t, 32-feature chunk c
+    bf16x8 w3[2];
     f32x4 b1[4];  // the accumulators start from the biases
     f32x4 b2[4];
     f32x4 b3;
 };
+
+// Hidden feature of K slot (lane group g, element j) of 32-feature chunk c.
+__device__ __forceinline__ int kslot_feature(int c, int g, int j) { return 16 * (2 * c + (j >> 2)) + 4 * g + (j & 3); }
 
 // bf16 bits of parameter i: stored as bf16, or rounded from fp32 as the
 // training kernels round them (mlp_round_kernel).
@@ -79,19 +90,17 @@ __device__ __forceinline__ uint16_t wbits(const float *__restrict__ w, int i) { 
 template <class W>
 __device__ __forceinline__ void load_frags(MlpFrags &f, const W *__restrict__ wb) {
     const int l = threadIdx.x & 63;
-    const int row = l & 15, kg = (l >> 4) * 4;
+    const int row = l & 15, g = l >> 4, kg = g * 4;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+        // layer 1: K slot (g, j) is input bit 8 g + j
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
+        for (int j = 0; j < 8; ++j) f.w1[t][j] = (short)wbits(wb, P_W1 + (16 * t + row) * kIn + 8 * g + j);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                f.w1[t][ks][j] = (short)wbits(wb, P_W1 + (16 * t + row) * kIn + 16 * ks + kg + j);
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                f.w2[t][ks][j] = (short)wbits(wb, P_W2 + (16 * t + row) * kH + 16 * ks + kg + j);
+            for (int j = 0; j < 8; ++j)
+                f.w2[t][c][j] = (short)wbits(wb, P_W2 + (16 * t + row) * kH + kslot_feature(c, g, j));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             f.b1[t][r] = bf2f(wbits(wb, P_B1 + 16 * t + kg + r));
@@ -99,32 +108,34 @@ __device__ __forceinline__ void load_frags(MlpFrags &f, const W *__restrict__ wb
         }
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            f.w3[ks][j] = row == 0 ? (short)wbits(wb, P_W3 + 16 * ks + kg + j) : (short)0;
+        for (int j = 0; j < 8; ++j)
+            f.w3[c][j] = row == 0 ? (short)wbits(wb, P_W3 + kslot_feature(c, g, j)) : (short)0;
     const float b3 = bf2f(wbits(wb, P_B3));
     f.b3 = (f32x4){b3, b3, b3, b3};
 }
 
-// ReLU(acc) rounded to bf16 (nearest even, the rounding of f2bf for finite
-// values) by the hardware conversion, two values per instruction; acc
-// already holds the bias.  The ReLU is an integer maximum with 0 on the bit
-// patterns: every negative float (and -0) has the sign bit set.
+// ReLU(acc) rounded to bf16: the hardware conversion (nearest even, the
+// rounding of f2bf for finite values, two values per instruction), then the
+// ReLU as a packed signed 16-bit maximum with 0 on the bf16 bit patterns
+// (every negative value, -0 included, has the sign bit set; rounding keeps
+// the sign, so this equals rounding the ReLU).  acc already holds the bias.
 typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ float relu_f(float v) {
-    const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, b > 0 ? b : 0);
-}
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc) {
-    u32x2 w;
-    w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){relu_f(acc[0]), relu_f(acc[1])}, bf16v2));
-    w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){relu_f(acc[2]), relu_f(acc[3])}, bf16v2));
-    return __builtin_bit_cast(bf16x4, w);
+    s16x2 h0 = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){acc[0], acc[1]}, bf16v2));
+    s16x2 h1 = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){acc[2], acc[3]}, bf16v2));
+    h0 = __builtin_elementwise_max(h0, (s16x2){0, 0});
+    h1 = __builtin_elementwise_max(h1, (s16x2){0, 0});
+    return (bf16x4){h0[0], h0[1], h1[0], h1[1]};
+}
+
+__device__ __forceinline__ f32x4 mfma32(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mfma_bf16x8, a),
+                                                   __builtin_bit_cast(mfma_bf16x8, b), c, 0, 0, 0);
 }
 
 // Network output for the 16 queries held by lanes 16*grp .. 16*grp+15 of the
@@ -133,34 +144,27 @@ __device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc) {
 __device__ __forceinline__ float mlp16(const MlpFrags &f, uint32_t q, int grp) {
     const int l = threadIdx.x & 63;
     const uint32_t a = (uint32_t)__shfl((int)q, 16 * grp + (l & 15), 64);
-    const int kg = (l >> 4) * 4;
-    bf16x4 xb[2];
+    const uint32_t bits = (a >> (8 * (l >> 4))) & 0xFFu;  // inputs 8 g .. 8 g + 7
+    bf16x8 xb;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xb[ks][j] = ((a >> (16 * ks + kg + j)) & 1u) ? (short)0x3F80 : (short)0;
+    for (int j = 0; j < 8; ++j) xb[j] = ((bits >> j) & 1u) ? (short)0x3F80 : (short)0;
     bf16x4 h1[4], h2[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        f32x4 acc = f.b1[t];
+    for (int t = 0; t < 4; ++t) h1[t] = relu_bf16(mfma32(f.w1[t], xb, f.b1[t]));
+    const bf16x8 k1[2] = {__builtin_shufflevector(h1[0], h1[1], 0, 1, 2, 3, 4, 5, 6, 7),
+                          __builtin_shufflevector(h1[2], h1[3], 0, 1, 2, 3, 4, 5, 6, 7)};
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w1[t][ks], xb[ks], acc, 0, 0, 0);
-        h1[t] = relu_bf16(acc);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        f32x4 acc = f.b2[t];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w2[t][ks], h1[ks], acc, 0, 0, 0);
-        h2[t] = relu_bf16(acc);
-    }
-    f32x4 acc = f.b3;
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.w3[ks], h2[ks], acc, 0, 0, 0);
+    for (int t = 0; t < 4; ++t) h2[t] = relu_bf16(mfma32(f.w2[t][1], k1[1], mfma32(f.w2[t][0], k1[0], f.b2[t])));
+    const bf16x8 k2[2] = {__builtin_shufflevector(h2[0], h2[1], 0, 1, 2, 3, 4, 5, 6, 7),
+                          __builtin_shufflevector(h2[2], h2[3], 0, 1, 2, 3, 4, 5, 6, 7)};
+    const f32x4 acc = mfma32(f.w3[1], k2[1], mfma32(f.w3[0], k2[0], f.b3));
     return acc[0];
 }
 
 // Network outputs for the 64 queries of a wave, each lane receiving its own.
+// The four groups run one after another: going through each layer with all
+// four together hides the latency of the dependent products but needs about
+// 180 registers, which costs the ranking kernel more occupancy than it gains.
 __device__ __forceinline__ float mlp64(const MlpFrags &f, uint32_t q) {
     const int l = threadIdx.x & 63;
     const float y0 = mlp16(f, q, 0), y1 = mlp16(f, q, 1), y2 = mlp16(f, q, 2), y3 = mlp16(f, q, 3);
