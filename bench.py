@@ -589,7 +589,7 @@ def row_batched(torch, mbr, steps: int):
                                                                f"H·x over all 169 sectors ({2 * tsz} B per row)")}
             # every launch shape of the product, for the record
             shapes = {}
-            for G in (-1, 0, 1, 2, 4):
+            for G in (-2, -1, 0, 1, 2, 4):
                 try:
                     mbr.hubbard_set_config(h, shape["k"], G, 512)
                 except mbr.MbrError:
@@ -720,7 +720,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--G", type=int, default=None,
                     help="fixed launch shape: alpha_up blocks per tile (0 = alpha_dn-stationary kernel, "
-                         "-1 = flat kernel); implies --no-tune")
+                         "-1 = flat kernel, -2 = block kernel for C_dn > 512); implies --no-tune")
     ap.add_argument("--block", type=int, default=512, help="tile-kernel block size with --G")
     ap.add_argument("--kernel-only", nargs="?", const="chain", choices=("chain", "anderson"),
                     help="only the H·x product of the headline chain (or of the impurity model over all "
@@ -808,8 +808,10 @@ def main():
     y = torch.empty_like(x)
     hv_ms = time_launches(torch, lambda: mbr.hubbard_apply(h, x, y), args.kernel_reps)
     alg_bytes = 16.0 * dim  # x read once + y written once, fp64
-    roof = hbm_roofline(alg_bytes, hv_ms, "hv_rows_kernel (plain H·x)")
-    roof["traffic"] = traffic_for("hv_rows_kernel<double,false,4,true>") if launch_cfg["G"] == 0 else None
+    hv_kernel_name = {0: "hv_rows_kernel<double,false,4,true>", -2: "hv_block_kernel<double,false,true>"}
+    kname = hv_kernel_name.get(launch_cfg["G"])
+    roof = hbm_roofline(alg_bytes, hv_ms, f"{(kname or 'H·x kernel').split('<')[0]} (plain H·x)")
+    roof["traffic"] = traffic_for(kname) if kname else None
     # context: with the up-hop gathers counted (8 B per hop changing alpha_up;
     # down-hop sources come from the row staged in LDS) the bytes that must
     # cross L2 per product

@@ -507,12 +507,15 @@ mbr_status mbr_hubbard_destroy(mbr_hubbard *h);
  * 0 selects the alpha_dn-stationary rows kernel (1024-lane workgroups, one
  * per CU, down-hop lists ranked once per launch shape) for every sector it
  * supports (at most 4095 spin-down configurations and 15 bonds) and the tile
- * kernel with two blocks for the rest; G in {1,2,4} selects the tile kernel
- * for every sector,
- * holding G alpha_up blocks per workgroup (the down-hop ranks of a lane are
- * reused G times); block: threads per workgroup of the tile kernel (256 or
- * 512).  tuned_ms is the autotuner's best time for one product (0 when not
- * tuned). */
+ * kernel with two blocks for the rest; -2 is G = 0 with the sectors of more
+ * than 512 spin-down configurations moved to the block kernel (one alpha_up
+ * block per 1024-lane workgroup, a workgroup per tile instead of one per CU,
+ * up-hop lists of every half state built once per launch shape); G in
+ * {1,2,4} selects the tile kernel for every sector, holding G alpha_up
+ * blocks per workgroup (the down-hop ranks of a lane are reused G times);
+ * block: threads per workgroup of the tile kernel (256 or 512).  Every shape
+ * sums each row's terms in the same order, so products are bitwise equal.
+ * tuned_ms is the autotuner's best time for one product (0 when not tuned). */
 typedef struct {
     int32_t k;
     int32_t G;
@@ -524,7 +527,7 @@ typedef struct {
 
 mbr_status mbr_hubbard_get_config(const mbr_hubbard *h, mbr_hubbard_cfg *cfg);
 
-/* Set the launch shape (k in 1..L, G in {-1,0,1,2,4}, block in {256,512}); EUNSUPPORTED
+/* Set the launch shape (k in 1..L, G in {-2,-1,0,1,2,4}, block in {256,512}); EUNSUPPORTED
  * when the tiles would not fit the LDS.  Lanczos handles created before the
  * change reject further steps (EINVAL): create them afterwards. */
 mbr_status mbr_hubbard_set_config(mbr_hubbard *h, int32_t k, int32_t G, int32_t block, void *stream);

@@ -82,8 +82,14 @@ struct mbr_hubbard {
     uint32_t rows_xcap = 0, rows_gmax = 1;
     int rows_R = 1, rows_grid = 0;
     bool t_uniform = true;              // all bonds share one amplitude
-    DevBuf d_lists;                     // rows kernel: down-hop lists per n_dn
+    DevBuf d_lists;                     // rows and block kernels: down-hop lists per n_dn
     std::vector<uint32_t> lists_ndn;    // n_dn of each list set, in storage order
+    std::vector<uint8_t> lists_blk;     // the set serves block-kernel sectors (their negated-copy offset)
+    std::vector<HvTile> block_tiles;    // block kernel (G = -2) tiles, one alpha_up block each, natural order
+    DevBuf d_bdesc;                     // their descriptors
+    uint32_t block_xoff[kXcd + 1] = {0};
+    uint32_t block_xcap = 0;            // largest C_dn + 1 of the block kernel's sectors
+    DevBuf d_up_tgt, d_up_coef, d_up_n; // block kernel: up-hop lists of every half state
     uint32_t n_slots = 0;
     StagTable tab;
     DevBuf d_hs_states, d_hs_energy, d_tiles, d_secs;
@@ -722,7 +728,9 @@ __device__ __forceinline__ void rows_pre_store(unsigned char *bb, size_t cs, uin
 // xb) in groups of four; the groups past kRowsDownFixed entries are skipped
 // when they are past the end of every list of the wave.  Uniform amplitude: the signed x values are summed (the
 // caller scales by t); otherwise each is weighted by its bond's amplitude.
-template <class T, bool UT, int W>
+// FIX: entries summed without a branch.  The padding adds +0 to a sum that
+// starts at +0 and so is never -0: FIX does not change the result.
+template <class T, bool UT, int W, int FIX = kRowsDownFixed>
 __device__ __forceinline__ T rows_down(const uint32_t (&hl)[W], const unsigned char *xb, const T *amp,
                                        bool valid) {
     const uint32_t n = valid ? (UT ? hl[W - 1] >> 16 : hl[W - 1]) : 0u;
@@ -731,7 +739,7 @@ __device__ __forceinline__ T rows_down(const uint32_t (&hl)[W], const unsigned c
     for (int u0 = 0; u0 < kRowsNB - 1; u0 += 4) {
         // the first groups run unconditionally (padding reads the zero): a
         // branch there would let the compiler sink the list load into it
-        if (u0 < kRowsDownFixed || (uint32_t)u0 < n) {
+        if (u0 < FIX || (uint32_t)u0 < n) {
             constexpr int kQ = 4;
             T v[kQ];
             T c[kQ];
@@ -1158,6 +1166,200 @@ __global__ void __launch_bounds__(kRowsBlock) hv_rows_kernel(HvArgs a) {
 }
 
 // ------------------------------------------------------------------------
+// Block kernel (launch shape G = -2) for sectors with C_dn > 512.  One
+// alpha_up block per 1024-lane workgroup and no loop over tiles: a workgroup
+// stages its block of x in LDS (x and -x, the layout the down-hop lists
+// address), sums its rows and exits, so a CU holds two of them, each with its
+// own loads in flight, where the rows kernel holds one that sweeps tile after
+// tile behind a barrier.  The up-hop targets and signed amplitudes of every
+// half state are listed once per launch shape (hv_uplists_kernel) and read
+// as scalars.  The workgroups of an XCD take one contiguous, cost-balanced
+// range of tiles, so the neighbouring alpha_up blocks that the up-hops gather
+// meet in that XCD's L2.  Terms are summed in the order of the rows kernel
+// (down-hops in list order, the diagonal, up-hops in bond order) with the same
+// fused operations, so the products are bitwise equal.
+// ------------------------------------------------------------------------
+constexpr int kBlockLanes = 1024;
+constexpr uint32_t kBlockMin = kBlockLanes / 2;  // C_dn above which a sector takes this kernel
+
+template <class T>
+struct BlockUpLists {
+    const uint32_t *tgt;  // [half state][kRowsNB]: target ranks in bond order, 0 past the hops
+    const T *coef;        // [half state][kRowsNB]: signed amplitudes, 0 past the hops
+    const uint32_t *n;    // [half state]: number of hops
+};
+
+// Up-hop lists of every half state (one lane each), with the ranks and signed
+// amplitudes that rows_uplists computes for a tile's blocks.
+template <class T>
+__global__ void __launch_bounds__(256) hv_uplists_kernel(HvArgs a, uint32_t n_hs, uint32_t *tgt, T *coef,
+                                                         uint32_t *cnt) {
+    const uint32_t hs = blockIdx.x * blockDim.x + threadIdx.x;
+    if (hs >= n_hs) return;
+    const uint32_t au = a.hs_states[hs];
+    uint32_t n = 0;
+    for (int b = 0; b < a.nb; ++b) {
+        const uint32_t bi = a.bij[b] & 0xFF, bj = a.bij[b] >> 8;
+        if (!(((au >> bi) ^ (au >> bj)) & 1)) continue;
+        tgt[(size_t)hs * kRowsNB + n] = rank_half<0>(au ^ a.bmask[b], a.rtab, a);
+        coef[(size_t)hs * kRowsNB + n] = (__popc(au & a.bbetw[b]) & 1) ? (T)a.bamp[b] : -(T)a.bamp[b];
+        ++n;
+    }
+    for (uint32_t u = n; u < (uint32_t)kRowsNB; ++u) {
+        tgt[(size_t)hs * kRowsNB + u] = 0u;
+        coef[(size_t)hs * kRowsNB + u] = (T)0;
+    }
+    cnt[hs] = n;
+}
+
+// LDS of the block kernel: x at byte 0 and -x at byte cs (cs = the down-hop
+// lists' offset of the negated copy), bond amplitudes, on-site U, reduction.
+__host__ __device__ inline size_t block_lds_bytes(uint32_t xcap, size_t tsz) {
+    const size_t cs = ((size_t)xcap * tsz + 15) & ~(size_t)15;
+    return 2 * cs + (size_t)(kRowsNB + kMaxSites) * tsz + kRowsWaves * sizeof(double);
+}
+
+template <class T, bool LZ, bool UT>
+__global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUpLists<T> up) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const size_t cs = ((size_t)a.xcap * sizeof(T) + 15) & ~(size_t)15;
+    T *xp = reinterpret_cast<T *>(smem);
+    T *xm = reinterpret_cast<T *>(smem + cs);
+    T *amp = reinterpret_cast<T *>(smem + 2 * cs);
+    T *ul = amp + kRowsNB;
+    double *red = reinterpret_cast<double *>(smem + 2 * cs + (size_t)(kRowsNB + kMaxSites) * sizeof(T));
+    uint32_t ti;
+    if (a.binned) {
+        const uint32_t xcd = blockIdx.x % kXcd;
+        ti = a.xoff[xcd] + blockIdx.x / kXcd;
+        if (ti >= a.xoff[xcd + 1]) return;  // whole workgroup: no barrier is skipped by part of it
+    } else {
+        ti = blockIdx.x;
+        if (ti >= a.n_tiles) return;
+    }
+    const int tid = threadIdx.x;
+    uint4 q[2];
+    rows_desc_load(a.rdesc, ti, q);
+    const RowsTile c = rows_desc_uniform(q);
+    const T *x = static_cast<const T *>(a.x);
+    T *out = static_cast<T *>(a.out);
+    const T *p = static_cast<const T *>(a.ep.p);
+    if (a.ep.basis_j) {
+        const int64_t j = *a.ep.basis_j;
+        x += (uint64_t)j * a.ep.basis_stride;
+        p = j > 0 ? x - a.ep.basis_stride : x;
+    }
+    const uint32_t cdn = c.cdn;
+    // Every load the workgroup needs before its barrier is issued first, so
+    // that they are in flight together: the block of x (vector), alpha_up's
+    // pattern, energy and up-hop lists (scalar).
+    const T *xs = x + c.base;
+    T pre[kRowsMaxR];
+#pragma unroll
+    for (int r = 0; r < kRowsMaxR; ++r) {
+        const uint32_t e = tid + r * kBlockLanes;
+        pre[r] = xs[e < cdn ? e : 0];
+    }
+    const uint32_t hsu = c.hs_up0;
+    // the 16-bit pattern from its aligned 32-bit word (a scalar load)
+    const uint32_t hw = reinterpret_cast<const uint32_t *>(a.hs_states)[hsu >> 1];
+    const uint32_t au = __builtin_amdgcn_readfirstlane((hw >> ((hsu & 1) * 16)) & 0xFFFFu);
+    const T eu = uniform_val((T)a.hs_energy[hsu]);
+    const uint32_t nu = __builtin_amdgcn_readfirstlane(up.n[hsu]);
+    const uint32_t *utb = up.tgt + (size_t)hsu * kRowsNB;
+    const T *ucb = up.coef + (size_t)hsu * kRowsNB;
+    const T *xsec = x + c.soff;
+    // all kRowsNB entries in scalar registers, read before any store (loads
+    // inside the row loop could not be hoisted past the stores to out)
+    uint32_t tg[kRowsNB];
+    T cf[kRowsNB];
+#pragma unroll
+    for (int h = 0; h < kRowsNB; ++h) {
+        tg[h] = __builtin_amdgcn_readfirstlane(utb[h]);
+        cf[h] = uniform_val(ucb[h]);
+    }
+    const T *src[kUpMax];
+#pragma unroll
+    for (int h = 0; h < kUpMax; ++h) src[h] = xsec + (uint64_t)tg[h] * cdn;
+    // the block of x, its negation, and a zero after it; amplitudes and U
+    // only where the sums read them (bond-dependent hopping, site-dependent U)
+#pragma unroll
+    for (int r = 0; r < kRowsMaxR; ++r) {
+        const uint32_t e = tid + r * kBlockLanes;
+        if (e < cdn) {
+            xp[e] = pre[r];
+            xm[e] = -pre[r];
+        }
+    }
+    if (tid == 0) xp[cdn] = (T)0;
+    if (!UT && tid < kRowsNB) amp[tid] = tid < a.nb ? (T)a.bamp[tid] : (T)0;
+    if (!a.U_uniform && tid < kMaxSites) ul[tid] = (T)a.U[tid];
+    const bool active = !a.ep.active || __builtin_amdgcn_readfirstlane(a.ep.active[c.sector]) != 0;
+    const bool has_p = LZ && a.ep.c2;
+    const T c1 = LZ ? uniform_val((T)a.ep.c1[c.sector]) : (T)1;
+    const T c2 = has_p ? uniform_val((T)a.ep.c2[c.sector]) : (T)0;
+    const T tu = (T)a.bamp[0];
+    constexpr int kWords = UT ? kRowsNB / 2 : kRowsNB;
+    const uint32_t *slists = static_cast<const uint32_t *>(a.lists) + (size_t)c.loff * kWords;
+    __syncthreads();
+    double dot = 0.0;
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < kRowsMaxR; ++r) {
+            const int rd = tid + r * kBlockLanes;
+            if (rd >= (int)cdn) break;
+            // the first kUpMax up-hop sources (past the hops: block 0 with
+            // coefficient 0) are in flight during the down-hop work
+            T g[kUpMax];
+#pragma unroll
+            for (int h = 0; h < kUpMax; ++h) g[h] = src[h][rd];
+            uint32_t hl[kWords];
+            rows_load_list(slists + (size_t)rd * kWords, hl);
+            const uint64_t row = c.base + (uint32_t)rd;
+            const T pv = has_p ? p[row] : (T)0;
+            const uint32_t adr = a.hs_states[c.hs_dn + rd];
+            const T edr = (T)a.hs_energy[c.hs_dn + rd];
+            const T acc = rows_down<T, UT, kWords, 8>(hl, smem, amp, true);
+            const T xv = xp[rd];
+            const T dg = eu + edr + rows_u_energy<T>(au & adr, a, ul);
+            T v = fma_t(dg, xv, UT ? tu * acc : acc);
+#pragma unroll
+            for (int h = 0; h < kUpMax; ++h) v = fma_t(cf[h], g[h], v);
+            // the rest in groups of four, as rows_up_tail sums them
+#pragma unroll
+            for (int h0 = kUpMax; h0 < kRowsNB; h0 += 4) {
+                if (nu <= (uint32_t)h0) break;
+                T g2[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) g2[q] = xsec[(uint64_t)tg[h0 + q] * cdn + rd];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v = fma_t(cf[h0 + q], g2[q], v);
+            }
+            if constexpr (LZ) {
+                const T uu = lz_out(v, c1, c2, pv, has_p);
+                out[row] = uu;
+                dot = __builtin_fma((double)xv, (double)uu, dot);
+            } else {
+                out[row] = v;
+            }
+        }
+    }
+    // the tile's partial of <x, u>: per wave, then wave 0 adds the 16 (the
+    // rows kernel's order for a one-block tile)
+    if (a.ep.partial) {
+        double v = dot;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        if (tid < 64) {
+            double w = tid < kRowsWaves ? red[tid] : 0.0;
+            for (int o = kRowsWaves / 2; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
+            if (tid == 0) a.ep.partial[c.slot] = active ? w : 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // Flat kernel.  Every row is independent work for one lane: no staged x, no
 // down-hop lists, no barrier between rows, so a CU holds as many waves as its
 // registers allow and their gathers overlap.  A 256-lane workgroup takes one
@@ -1430,7 +1632,7 @@ size_t lds_bytes_for(const mbr_hubbard *h, size_t tsz) {
 template <class T, int NCH, bool LZ>
 mbr_status launch_g(const mbr_hubbard *h, const HvArgs &a, unsigned grid, size_t lds, hipStream_t s) {
     auto pick = [&]() {
-        switch (h->G == 0 ? 2 : h->G) {
+        switch (h->G <= 0 ? 2 : h->G) {
             case 1: return hv_kernel<T, NCH, LZ, 1>;
             case 2: return hv_kernel<T, NCH, LZ, 2>;
             default: return hv_kernel<T, NCH, LZ, 4>;
@@ -1515,6 +1717,21 @@ mbr_status launch_rows(const mbr_hubbard *h, const HvArgs &a, unsigned cap, int 
     }
 }
 
+// Block kernel over `grid` workgroups (descriptors and ranges set in a).
+template <class T, bool LZ>
+mbr_status launch_block(const mbr_hubbard *h, HvArgs a, unsigned grid, hipStream_t s) {
+    auto kern = h->t_uniform ? hv_block_kernel<T, LZ, true> : hv_block_kernel<T, LZ, false>;
+    a.xcap = h->block_xcap;
+    const size_t lds = block_lds_bytes(h->block_xcap, sizeof(T));
+    if (lds > 64 * 1024)
+        MBR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    BlockUpLists<T> up{h->d_up_tgt.as<uint32_t>(), h->d_up_coef.as<T>(), h->d_up_n.as<uint32_t>()};
+    if (grid) kern<<<grid, kBlockLanes, lds, s>>>(a, up);
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
 template <class T, int NCH>
 mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpilogue &ep,
                     hipStream_t s) {
@@ -1533,6 +1750,11 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
         if (!h->flat_tiles.empty()) {
             if (ep.c1) return launch_flat<T, NCH, true>(a, ep.n_tiles, s);
             return launch_flat<T, NCH, false>(a, ep.n_tiles, s);
+        }
+        if (h->hsec[ep.sector].blk) {
+            a.rdesc = h->d_rdesc_slot.as<RowsTileDesc>() + h->hsec[ep.sector].slot0;
+            if (ep.c1) return launch_block<T, true>(h, a, ep.n_tiles, s);
+            return launch_block<T, false>(h, a, ep.n_tiles, s);
         }
         if (h->hsec[ep.sector].rows) {
             // the sector's tiles are the slot range starting at its first slot
@@ -1564,6 +1786,18 @@ mbr_status launch_t(const mbr_hubbard *h, const void *x, void *out, const HvEpil
         }
         if (ep.c1) return launch_flat<T, NCH, true>(a, grid, s);
         return launch_flat<T, NCH, false>(a, grid, s);
+    }
+    if (!h->block_tiles.empty()) {
+        HvArgs ab = a;
+        ab.rdesc = h->d_bdesc.as<RowsTileDesc>();
+        ab.n_tiles = (uint32_t)h->block_tiles.size();
+        ab.binned = 1;
+        uint32_t most = 0;
+        for (int i = 0; i <= kXcd; ++i) ab.xoff[i] = h->block_xoff[i];
+        for (int i = 0; i < kXcd; ++i) most = std::max(most, h->block_xoff[i + 1] - h->block_xoff[i]);
+        const unsigned grid = most * kXcd;
+        if (ep.c1) MBR_TRY((launch_block<T, true>(h, ab, grid, s)));
+        else MBR_TRY((launch_block<T, false>(h, ab, grid, s)));
     }
     if (!h->rows_tiles.empty()) {
         HvArgs ar = a;
@@ -1629,11 +1863,13 @@ mbr_status build_lists(mbr_hubbard *h, uint32_t lrows, hipStream_t s) {
     MBR_TRY(h->d_lists.alloc((size_t)lrows * words * 4));
     HvArgs a{};
     fill_args(h, a, nullptr, nullptr, HvEpilogue{});
-    const uint32_t cs =
+    const uint32_t rcs =
         (uint32_t)rows_lds_layout(a.rtab_entries, h->rows_xcap, h->rows_gmax, tsz).cs;
+    const uint32_t bcs = (uint32_t)(((size_t)h->block_xcap * tsz + 15) & ~(size_t)15);
     uint32_t row0 = 0;
     for (size_t li = 0; li < h->lists_ndn.size(); ++li) {
         const uint32_t nd = h->lists_ndn[li];
+        const uint32_t cs = h->lists_blk[li] ? bcs : rcs;
         const uint32_t cdn = (uint32_t)binom(h->L, (int)nd);
         uint32_t *lists = h->d_lists.as<uint32_t>() + (size_t)row0 * words;
         const unsigned grid = (cdn + 255) / 256;
@@ -1647,13 +1883,35 @@ mbr_status build_lists(mbr_hubbard *h, uint32_t lrows, hipStream_t s) {
     return MBR_OK;
 }
 
+// Up-hop lists of every half state for the block kernel.
+mbr_status build_uplists(mbr_hubbard *h, hipStream_t s) {
+    const uint32_t n_hs = h->hs_off[h->L + 1];
+    const size_t tsz = h->precision == MBR_F64 ? 8 : 4;
+    MBR_TRY(h->d_up_tgt.alloc((size_t)n_hs * kRowsNB * 4));
+    MBR_TRY(h->d_up_coef.alloc((size_t)n_hs * kRowsNB * tsz));
+    MBR_TRY(h->d_up_n.alloc((size_t)n_hs * 4));
+    HvArgs a{};
+    fill_args(h, a, nullptr, nullptr, HvEpilogue{});
+    const unsigned grid = (n_hs + 255) / 256;
+    if (tsz == 8)
+        hv_uplists_kernel<double><<<grid, 256, 0, s>>>(a, n_hs, h->d_up_tgt.as<uint32_t>(), h->d_up_coef.as<double>(),
+                                                       h->d_up_n.as<uint32_t>());
+    else
+        hv_uplists_kernel<float><<<grid, 256, 0, s>>>(a, n_hs, h->d_up_tgt.as<uint32_t>(), h->d_up_coef.as<float>(),
+                                                      h->d_up_n.as<uint32_t>());
+    MBR_HIP(hipGetLastError());
+    return MBR_OK;
+}
+
 // Rebuild the rank table, tiles, work ranges and LDS budgets for (k, G, block).
-// G = 0 selects the alpha_dn-stationary kernel for every sector it supports.
+// G = 0 selects the alpha_dn-stationary kernel for every sector it supports;
+// G = -2 the same, but sectors with C_dn > 512 go to the block kernel.
 mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     const int L = h->L;
     if (k < 1 || k > L || k > 16) MBR_FAIL(MBR_EINVAL, "k=%d outside 1..L", k);
-    if (G != -1 && G != 0 && G != 1 && G != 2 && G != 4) MBR_FAIL(MBR_EINVAL, "G=%d not in {-1,0,1,2,4}", G);
+    if (G < -2 || G > 4 || G == 3) MBR_FAIL(MBR_EINVAL, "G=%d not in {-2,-1,0,1,2,4}", G);
     const bool flat = G == -1;
+    const bool rows_shape = G == 0 || G == -2;
     if (block != 256 && block != 512) MBR_FAIL(MBR_EINVAL, "block=%d not in {256,512}", block);
     StagTable tab;
     MBR_TRY(stag_build(tab, L, k, L, 2, s));
@@ -1661,13 +1919,14 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     if ((((size_t)tab.nrows << k) * 2) > 64 * 1024)
         MBR_FAIL(MBR_EUNSUPPORTED, "k=%d: half table over 64 KiB", k);
     const size_t tsz = h->precision == MBR_F64 ? 8 : 4;
-    const int Gt = G == 0 ? 2 : G;  // tile-kernel blocks for sectors the rows kernel does not take
+    const int Gt = rows_shape ? 2 : G;  // tile-kernel blocks for sectors the rows kernel does not take
     const size_t xbudget = (Gt == 4 ? 112 : 56) * 1024;
     std::vector<HvSector> hsec;
-    std::vector<HvTile> tiles, rows_tiles, other_tiles, flat_tiles;
+    std::vector<HvTile> tiles, rows_tiles, other_tiles, flat_tiles, block_tiles;
     uint64_t off = 0;
-    uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0, rows_gmax = 1, lrows = 0;
+    uint32_t slot = 0, xcap = 0, upcap = 0, maxblk = 0, rows_xcap = 0, rows_gmax = 1, lrows = 0, block_xcap = 0;
     std::vector<uint32_t> lists_ndn, lists_rows;
+    std::vector<uint8_t> lists_blk;
     int rows_R = 1;
     bool t_uniform = true;  // every bond has one amplitude (the rows kernel's uniform-hopping instances)
     for (auto &b : h->bonds) t_uniform = t_uniform && b.t == h->bonds[0].t;
@@ -1679,10 +1938,18 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
         sc.cdn = (uint32_t)binom(L, h->secs[si].n_dn);
         sc.hs_up = h->hs_off[h->secs[si].n_up];
         sc.hs_dn = h->hs_off[h->secs[si].n_dn];
-        sc.rows = (G == 0 && sc.cdn + 1 <= kRowsMaxX && h->nb <= kRowsNB - 1) ? 1 : 0;
+        sc.rows = (rows_shape && sc.cdn + 1 <= kRowsMaxX && h->nb <= kRowsNB - 1) ? 1 : 0;
+        sc.blk = (G == -2 && sc.rows && sc.cdn > kBlockMin) ? 1 : 0;
+        if (sc.blk) sc.rows = 0;
         sc.magic = sc.cdn == 1 ? 0xFFFFFFFFu : (uint32_t)((1ull << 32) / sc.cdn);
         uint32_t nblk;
-        if (flat) {
+        if (sc.blk) {
+            sc.wide = 1;
+            sc.x_lds = 1;
+            sc.gp = 1;
+            sc.R = (sc.cdn + kBlockLanes - 1) / kBlockLanes;
+            nblk = 1;
+        } else if (flat) {
             sc.wide = 0;
             sc.x_lds = 0;
             nblk = std::max<uint32_t>(1, kFlatRows / sc.cdn);
@@ -1729,7 +1996,10 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             t.rup0 = r;
             t.nblk = std::min(nblk, sc.cup - r);
             t.slot = slot++;
-            if (flat) {
+            if (sc.blk) {
+                block_xcap = std::max(block_xcap, sc.cdn + 1);
+                block_tiles.push_back(t);
+            } else if (flat) {
                 flat_tiles.push_back(t);
             } else if (sc.rows) {
                 rows_xcap = std::max(rows_xcap, t.nblk * (sc.cdn + 1));
@@ -1743,13 +2013,15 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             tiles.push_back(t);
         }
         sc.nslots = slot - sc.slot0;
-        if (sc.rows) {  // down-hop lists are shared by the sectors of one n_dn
+        if (sc.rows || sc.blk) {  // down-hop lists are shared by the sectors of one n_dn
             const uint32_t nd = (uint32_t)h->secs[si].n_dn;
             auto it = std::find(lists_ndn.begin(), lists_ndn.end(), nd);
             const size_t li = (size_t)(it - lists_ndn.begin());
             if (it == lists_ndn.end()) {
+                // one n_dn is one C_dn, so its sectors all take the same kernel
                 lists_ndn.push_back(nd);
                 lists_rows.push_back(lrows);
+                lists_blk.push_back(sc.blk ? 1 : 0);
                 lrows += sc.cdn;
             }
             sc.loff = lists_rows[li];
@@ -1765,6 +2037,9 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     if (rows_grid < kXcd) rows_grid = kXcd;
     const std::vector<uint32_t> rr = balanced_ranges(rows_tiles, hsec, kXcd);
     const std::vector<uint32_t> fr = balanced_ranges(flat_tiles, hsec, kXcd);
+    const std::vector<uint32_t> br = balanced_ranges(block_tiles, hsec, kXcd);
+    if (!block_tiles.empty() && block_lds_bytes(block_xcap, tsz) > kLdsMax)
+        MBR_FAIL(MBR_EUNSUPPORTED, "block kernel needs %zu bytes of LDS", block_lds_bytes(block_xcap, tsz));
     const size_t rows_lds = rows_lds_layout((uint32_t)((uint64_t)tab.nrows << k), rows_xcap, rows_gmax, tsz).total;
     if (!rows_tiles.empty() && rows_lds > kLdsMax) MBR_FAIL(MBR_EUNSUPPORTED, "rows kernel needs %zu bytes of LDS", rows_lds);
     // commit
@@ -1788,6 +2063,10 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     h->rows_xcap = rows_xcap;
     h->rows_R = rows_R;
     h->lists_ndn = lists_ndn;
+    h->lists_blk = lists_blk;
+    h->block_tiles = block_tiles;
+    h->block_xcap = block_xcap;
+    for (int b = 0; b <= kXcd; ++b) h->block_xoff[b] = br[b];
     h->rows_gmax = rows_gmax;
     h->rows_grid = rows_grid;
     h->t_uniform = t_uniform;
@@ -1804,21 +2083,25 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
             d.slot = t.slot;
             return d;
         };
-        for (auto &t : rows_tiles) {  // field widths of the packed descriptor
-            const HvSector &sc = hsec[t.sector];
-            if (sc.cdn > 0xFFF || sc.gp > 0xFF || t.nblk > 0xFFF || sc.hs_up + t.rup0 > 0xFFFF ||
-                sc.hs_dn > 0xFFFF || sc.loff > 0xFFFF || t.sector > 0xFFFF)
-                MBR_FAIL(MBR_EUNSUPPORTED, "rows-kernel tile descriptor out of range");
-        }
-        std::vector<RowsTileDesc> rd, rs;
+        for (const auto *tl : {&rows_tiles, &block_tiles})
+            for (auto &t : *tl) {  // field widths of the packed descriptor
+                const HvSector &sc = hsec[t.sector];
+                if (sc.cdn > 0xFFF || sc.gp > 0xFF || t.nblk > 0xFFF || sc.hs_up + t.rup0 > 0xFFFF ||
+                    sc.hs_dn > 0xFFFF || sc.loff > 0xFFFF || t.sector > 0xFFFF)
+                    MBR_FAIL(MBR_EUNSUPPORTED, "rows-kernel tile descriptor out of range");
+            }
+        std::vector<RowsTileDesc> rd, rs, bd;
         for (auto &t : rows_tiles) rd.push_back(mk(t));
+        for (auto &t : block_tiles) bd.push_back(mk(t));
         for (auto &t : tiles) rs.push_back(mk(t));
         MBR_TRY(upload(h->d_rdesc, rd.data(), rd.size() * sizeof(RowsTileDesc), s));
+        MBR_TRY(upload(h->d_bdesc, bd.data(), bd.size() * sizeof(RowsTileDesc), s));
         MBR_TRY(upload(h->d_rdesc_slot, rs.data(), rs.size() * sizeof(RowsTileDesc), s));
     }
     for (int b = 0; b <= kXcd; ++b) h->rows_xoff[b] = rr[b];
     MBR_TRY(upload(h->d_secs, h->hsec.data(), h->hsec.size() * sizeof(HvSector), s));
     h->lds_bytes = std::max(other_tiles.empty() ? 0 : lds_bytes_for(h, tsz), rows_tiles.empty() ? 0 : rows_lds);
+    if (!block_tiles.empty()) h->lds_bytes = std::max(h->lds_bytes, block_lds_bytes(block_xcap, tsz));
     if (!flat_tiles.empty())
         h->lds_bytes = std::max<size_t>(h->lds_bytes, ((((size_t)h->tab.nrows << h->tab.k) * 2 + 15) & ~(size_t)15) +
                                                           4 * sizeof(double));
@@ -1832,6 +2115,7 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
     h->grid -= h->grid % kXcd;
     if (h->grid < kXcd) h->grid = kXcd;
     MBR_TRY(build_lists(h, lrows, s));
+    if (!block_tiles.empty()) MBR_TRY(build_uplists(h, s));
     h->generation++;
     return MBR_OK;
 }
@@ -2142,9 +2426,9 @@ mbr_status mbr_hubbard_autotune(mbr_hubbard *h, int32_t reps, void *stream) {
     int bk = h->k, bG = h->G, bb = h->block;
     double best = 1e30;
     for (int k : ks)
-        for (int G : {-1, 0, 1, 2, 4})
+        for (int G : {-2, -1, 0, 1, 2, 4})
             for (int block : {256, 512}) {
-                if (G <= 0 && block != 512) continue;  // the rows and flat kernels have one block size each
+                if (G <= 0 && block != 512) continue;  // the rows, block and flat kernels have one block size each
                 if (configure(h, k, G, block, s) != MBR_OK) continue;
                 HvEpilogue ep{};
                 if (hubbard_launch(h, bx.p, by.p, ep, s) != MBR_OK) continue;

@@ -29,6 +29,7 @@ struct HvSector {
     uint32_t R;       // rows kernel: alpha_dn values per lane
     uint32_t loff;    // rows kernel: first down-hop list row of the sector's n_dn
     uint32_t magic;   // flat kernel: floor(2^32 / C_dn), to split a row index into (alpha_up, alpha_dn)
+    uint32_t blk;     // handled by the block kernel (launch shape G = -2): one alpha_up block per workgroup
 };
 
 // Epilogue: y = H x (plain), or u = c1[s] (H x)_i - c2[s] p_i written to `out`

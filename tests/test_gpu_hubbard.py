@@ -116,7 +116,16 @@ def test_chain_l14_all_rows():
     # launch shape (other shapes give bitwise equal products, tested below)
     L = 14
     h = _check_apply(L, OH.chain_bonds(L), [(7, 7)], [4.0] * L, None, mbr.F64, seed=2)
-    say("L=14 launch shape", mbr.hubbard_get_config(h))
+    cfg = mbr.hubbard_get_config(h)
+    say("L=14 launch shape", cfg)
+    # the block kernel (G = -2), the bench's launch shape when the autotuner
+    # picks it, gives the same bits as the default shape checked above
+    xd = _dev(2 * synth.uniform01(2, h.dim) - 1, mbr.F64)
+    y0, y1 = torch.empty_like(xd), torch.empty_like(xd)
+    mbr.hubbard_apply(h, xd, y0)
+    mbr.hubbard_set_config(h, cfg["k"], -2, 512)
+    mbr.hubbard_apply(h, xd, y1)
+    assert torch.equal(y0, y1)
 
 
 @pytest.mark.timeout(600)
@@ -265,10 +274,12 @@ def test_lanczos_free_fermions_l10():
         assert abs(e0[si] - want) <= 1e-9 * abs(want)
 
 
-def test_lanczos_chain_l14_200_steps_fp64():
+@pytest.mark.parametrize("G", [0, -2])
+def test_lanczos_chain_l14_200_steps_fp64(G):
     g = json.load(open(os.path.join(GOLD, "hubbard_chain_L14.json")))
     L = g["L"]
     h = mbr.hubbard_create(L, OH.chain_bonds(L), [(g["n_up"], g["n_dn"])], U=[g["U"]] * L)
+    mbr.hubbard_set_config(h, mbr.hubbard_get_config(h)["k"], G, 512)
     e0, nst, a, b = _run_lanczos(h, g["lanczos_steps"], seed=g["start_seed"])
     say("L14 E0", e0[0], g["e0_exact"], g["e0_lanczos"])
     assert nst[0] == g["lanczos_steps"]
@@ -298,7 +309,7 @@ def test_lanczos_anderson_169_sectors_mixed():
 def _shapes_equal(h, x, ks):
     ref = None
     for k in ks:
-        for G in (-1, 0, 1, 2, 4):
+        for G in (-2, -1, 0, 1, 2, 4):
             for block in ((512,) if G <= 0 else (256, 512)):
                 mbr.hubbard_set_config(h, k, G, block)
                 y = torch.empty_like(x)
@@ -323,7 +334,7 @@ def test_every_launch_shape_gives_identical_products():
         mbr.hubbard_set_config(h, 7, 3, 512)
     cfg = mbr.hubbard_autotune(h, reps=2)
     say("autotuned", cfg)
-    assert cfg["tuned_ms"] > 0 and cfg["G"] in (-1, 0, 1, 2, 4)
+    assert cfg["tuned_ms"] > 0 and cfg["G"] in (-2, -1, 0, 1, 2, 4)
     y = torch.empty_like(x)
     mbr.hubbard_apply(h, x, y)
     assert torch.equal(y, ref)
@@ -402,12 +413,13 @@ def test_lanczos_rejects_stale_launch_shape():
         mbr.lanczos_step(lz, 1)
 
 
-@pytest.mark.parametrize("G", [-1, 0])
+@pytest.mark.parametrize("G", [-2, -1, 0])
 def test_anderson_flat_and_rows_kernels_bitwise_equal_fp32(G):
-    """All 169 impurity-model sectors in fp32: the flat kernel (G = -1) and the
-    rows kernel (G = 0) give the same bits, sector sizes 1 to 853,776 and C_dn
-    from 1 to 924 included; the rows kernel result is the one checked against
-    the oracle row by row above."""
+    """All 169 impurity-model sectors in fp32: the flat kernel (G = -1), the
+    block kernel for C_dn > 512 (G = -2) and the rows kernel (G = 0) give the
+    same bits, sector sizes 1 to 853,776 and C_dn from 1 to 924 included; the
+    rows kernel result is the one checked against the oracle row by row
+    above."""
     L = 12
     eps_b, V = synth.anderson_parameters(5, 11)
     eps = [-4.0] + list(eps_b)
@@ -455,6 +467,62 @@ def test_chain_l10_every_row_and_launch_shapes(prec):
         want, ab = _oracle_apply_all(OH.sector(L, nu, nd), tl, x[o0:o1])
         bad = np.abs(y[o0:o1] - want) > 64 * eps_p * ab + 1e-300
         assert not bad.any(), (nu, nd, np.nonzero(bad)[0][:5])
+
+
+@pytest.mark.parametrize("bonds_kind,prec", [("chain", 0), ("chain", 1), ("star", 0), ("star", 1)])
+def test_block_kernel_every_row_and_lanczos(bonds_kind, prec):
+    """The block kernel (G = -2: sectors with C_dn > 512, one alpha_up block
+    per workgroup) beside the rows kernel's sectors: uniform hopping on a
+    periodic L=12 chain and bond-dependent amplitudes with site energies on the
+    impurity star, fp64 and fp32.  Every row against the oracle, and the
+    product bitwise equal to that of the rows kernel (G = 0), which sums the
+    same terms in the same order.  Lanczos (plain and per-sector launches): in
+    fp64 the rows kernel also takes one alpha_up block per tile for these
+    sectors, so the per-tile partial sums of <x, u> and the coefficients are
+    bitwise equal; in fp32 it packs three or four blocks per tile, so the
+    partials are grouped differently and the coefficients agree to rounding."""
+    L = 12
+    if bonds_kind == "chain":
+        bonds, U, eps = OH.chain_bonds(L, periodic=True), [3.0] * L, None
+    else:
+        eps_b, V = synth.anderson_parameters(6, L - 1)
+        bonds, U, eps = OH.star_bonds(V), [6.0] + [0.0] * (L - 1), [-3.0] + list(eps_b)
+    # C_dn = 924, 792, 792 (block kernel), 66 and 1 (rows kernel)
+    sectors = [(6, 6), (5, 7), (8, 5), (3, 2), (4, 0)]
+    h = mbr.hubbard_create(L, bonds, sectors, U=U, eps=eps, precision=prec)
+    cfg = mbr.hubbard_get_config(h)
+    x = 2 * synth.uniform01(41, h.dim) - 1
+    if prec == mbr.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x, prec)
+    ys = []
+    for G in (0, -2):
+        mbr.hubbard_set_config(h, cfg["k"], G, 512)
+        assert mbr.hubbard_get_config(h)["G"] == G
+        y = torch.empty_like(xd)
+        mbr.hubbard_apply(h, xd, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    y = ys[1].cpu().numpy().astype(np.float64)
+    tl = OH.terms(L, bonds, U, eps)
+    eps_p = EPS64 if prec == mbr.F64 else EPS32
+    for si, (nu, nd) in enumerate(sectors):
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        want, ab = _oracle_apply_all(OH.sector(L, nu, nd), tl, x[o0:o1])
+        bad = np.abs(y[o0:o1] - want) > 64 * eps_p * ab + 1e-300
+        assert not bad.any(), (nu, nd, np.nonzero(bad)[0][:5])
+    # Lanczos: the fused epilogue and the per-tile partial sums of <x, u>
+    for batched in (True, False):
+        rs = []
+        for G in (0, -2):
+            mbr.hubbard_set_config(h, cfg["k"], G, 512)
+            rs.append(_run_lanczos(h, 30, seed=7, batched=batched))
+        assert np.array_equal(rs[0][1], rs[1][1])  # steps done
+        for i in (0, 2, 3):
+            if prec == mbr.F64:
+                assert np.array_equal(rs[0][i], rs[1][i]), (batched, i)
+            else:
+                assert np.allclose(rs[0][i], rs[1][i], rtol=1e-5, atol=1e-6), (batched, i)
 
 
 @pytest.mark.parametrize("L,sectors,prec", [(6, [(3, 3), (2, 4), (0, 3), (6, 6)], 0),
