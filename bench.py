@@ -622,6 +622,8 @@ def row_chain(torch, mbr, steps: int):
     for name, prec, reorth in (("fp64", mbr.F64, False), ("fp32", mbr.F32, False),
                                ("fp64_reorth", mbr.F64, True), ("fp32_reorth", mbr.F32, True)):
         h = mbr.hubbard_create(L, chain_bonds(L), [(NUP, NDN)], U=[U] * L, precision=prec)
+        mbr.hubbard_autotune(h, reps=5)
+        shape = mbr.hubbard_get_config(h)
         v0 = torch.from_numpy(synth.start_vector(SEED, h.dim)).cuda()
         lz = mbr.lanczos_create(h, steps, reorth=reorth, use_graph=True)
         mbr.lanczos_start(lz, v0)
@@ -634,7 +636,8 @@ def row_chain(torch, mbr, steps: int):
         dt = time.perf_counter() - t0
         e0, _ = mbr.lanczos_result(lz)
         res[name] = {"value": steps / dt, "unit": "Lanczos steps/s", "ms_per_step": dt * 1e3 / steps,
-                     "e0": float(e0[0]), "rel_err_vs_oracle": abs(e0[0] - gold) / abs(gold)}
+                     "e0": float(e0[0]), "rel_err_vs_oracle": abs(e0[0] - gold) / abs(gold),
+                     "launch": {kk: shape[kk] for kk in ("k", "G", "block")}}
         if not reorth:
             x = torch.zeros(h.dim, dtype=torch.float32 if prec == mbr.F32 else torch.float64, device="cuda")
             x.copy_(v0)
