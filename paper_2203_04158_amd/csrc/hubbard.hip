@@ -1213,10 +1213,11 @@ __global__ void __launch_bounds__(256) hv_uplists_kernel(HvArgs a, uint32_t n_hs
 }
 
 // LDS of the block kernel: x at byte 0 and -x at byte cs (cs = the down-hop
-// lists' offset of the negated copy), bond amplitudes, on-site U, reduction.
+// lists' offset of the negated copy), bond amplitudes, on-site U, reduction,
+// then alpha_up's up-hop targets and coefficients.
 __host__ __device__ inline size_t block_lds_bytes(uint32_t xcap, size_t tsz) {
     const size_t cs = ((size_t)xcap * tsz + 15) & ~(size_t)15;
-    return 2 * cs + (size_t)(kRowsNB + kMaxSites) * tsz + kRowsWaves * sizeof(double);
+    return 2 * cs + (size_t)(kRowsNB + kMaxSites) * tsz + kRowsWaves * sizeof(double) + (size_t)kRowsNB * (4 + tsz);
 }
 
 template <class T, bool LZ, bool UT>
@@ -1228,6 +1229,8 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
     T *amp = reinterpret_cast<T *>(smem + 2 * cs);
     T *ul = amp + kRowsNB;
     double *red = reinterpret_cast<double *>(smem + 2 * cs + (size_t)(kRowsNB + kMaxSites) * sizeof(T));
+    uint32_t *lt = reinterpret_cast<uint32_t *>(red + kRowsWaves);
+    T *lc = reinterpret_cast<T *>(lt + kRowsNB);
     uint32_t ti;
     if (a.binned) {
         const uint32_t xcd = blockIdx.x % kXcd;
@@ -1269,18 +1272,24 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
     const uint32_t *utb = up.tgt + (size_t)hsu * kRowsNB;
     const T *ucb = up.coef + (size_t)hsu * kRowsNB;
     const T *xsec = x + c.soff;
-    // all kRowsNB entries in scalar registers, read before any store (loads
-    // inside the row loop could not be hoisted past the stores to out)
-    uint32_t tg[kRowsNB];
-    T cf[kRowsNB];
+    // the first kUpMax entries in scalar registers; all of them in LDS for
+    // the tail (reloading them from memory inside the row loop, past the
+    // stores to out, costs a round trip per row; holding all sixteen in
+    // scalar registers leaves too few of those for two workgroups per CU)
+    // (sources as 32-bit byte offsets in the sector, which configure keeps
+    // below 4 GiB: one scalar register each instead of a pointer's two)
+    T cf[kUpMax];
+    uint32_t sob[kUpMax];
 #pragma unroll
-    for (int h = 0; h < kRowsNB; ++h) {
-        tg[h] = __builtin_amdgcn_readfirstlane(utb[h]);
+    for (int h = 0; h < kUpMax; ++h) {
+        sob[h] = __builtin_amdgcn_readfirstlane(utb[h]) * cdn * (uint32_t)sizeof(T);
         cf[h] = uniform_val(ucb[h]);
     }
-    const T *src[kUpMax];
-#pragma unroll
-    for (int h = 0; h < kUpMax; ++h) src[h] = xsec + (uint64_t)tg[h] * cdn;
+    const unsigned char *xsb = reinterpret_cast<const unsigned char *>(xsec);
+    if (tid < kRowsNB) {
+        lt[tid] = utb[tid];
+        lc[tid] = ucb[tid];
+    }
     // the block of x, its negation, and a zero after it; amplitudes and U
     // only where the sums read them (bond-dependent hopping, site-dependent U)
 #pragma unroll
@@ -1312,7 +1321,8 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
             // coefficient 0) are in flight during the down-hop work
             T g[kUpMax];
 #pragma unroll
-            for (int h = 0; h < kUpMax; ++h) g[h] = src[h][rd];
+            for (int h = 0; h < kUpMax; ++h)
+                g[h] = *reinterpret_cast<const T *>(xsb + (sob[h] + (uint32_t)rd * (uint32_t)sizeof(T)));
             uint32_t hl[kWords];
             rows_load_list(slists + (size_t)rd * kWords, hl);
             const uint64_t row = c.base + (uint32_t)rd;
@@ -1325,16 +1335,7 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
             T v = fma_t(dg, xv, UT ? tu * acc : acc);
 #pragma unroll
             for (int h = 0; h < kUpMax; ++h) v = fma_t(cf[h], g[h], v);
-            // the rest in groups of four, as rows_up_tail sums them
-#pragma unroll
-            for (int h0 = kUpMax; h0 < kRowsNB; h0 += 4) {
-                if (nu <= (uint32_t)h0) break;
-                T g2[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) g2[q] = xsec[(uint64_t)tg[h0 + q] * cdn + rd];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v = fma_t(cf[h0 + q], g2[q], v);
-            }
+            v = rows_up_tail<T, true>(xsec, lt, lc, cdn, (uint32_t)rd, nu, v);
             if constexpr (LZ) {
                 const T uu = lz_out(v, c1, c2, pv, has_p);
                 out[row] = uu;
@@ -1939,7 +1940,8 @@ mbr_status configure(mbr_hubbard *h, int k, int G, int block, hipStream_t s) {
         sc.hs_up = h->hs_off[h->secs[si].n_up];
         sc.hs_dn = h->hs_off[h->secs[si].n_dn];
         sc.rows = (rows_shape && sc.cdn + 1 <= kRowsMaxX && h->nb <= kRowsNB - 1) ? 1 : 0;
-        sc.blk = (G == -2 && sc.rows && sc.cdn > kBlockMin) ? 1 : 0;
+        // (the block kernel addresses a sector with 32-bit byte offsets)
+        sc.blk = (G == -2 && sc.rows && sc.cdn > kBlockMin && (uint64_t)sc.cup * sc.cdn * tsz <= 0xFFFFFFFFull) ? 1 : 0;
         if (sc.blk) sc.rows = 0;
         sc.magic = sc.cdn == 1 ? 0xFFFFFFFFu : (uint32_t)((1ull << 32) / sc.cdn);
         uint32_t nblk;
