@@ -525,6 +525,41 @@ def test_block_kernel_every_row_and_lanczos(bonds_kind, prec):
                 assert np.allclose(rs[0][i], rs[1][i], rtol=1e-5, atol=1e-6), (batched, i)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_kernel_two_rows_per_lane_l13(prec):
+    """C_dn = 1716 (L = 13, six or seven spin-down fermions): each lane of a
+    block-kernel workgroup sums two rows, the second with 692 of 1024 lanes
+    active; open chain with a next-nearest bond.  Bitwise equal to the rows
+    kernel on every row, and sampled rows against the oracle."""
+    L = 13
+    bonds = OH.chain_bonds(L, periodic=False) + [(0, 2, 0.3)]
+    sectors = [(6, 7), (2, 6), (7, 1)]
+    h = mbr.hubbard_create(L, bonds, sectors, U=[2.0] * L, precision=prec)
+    cfg = mbr.hubbard_get_config(h)
+    x = 2 * synth.uniform01(43, h.dim) - 1
+    if prec == mbr.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x, prec)
+    ys = []
+    for G in (0, -2):
+        mbr.hubbard_set_config(h, cfg["k"], G, 512)
+        y = torch.empty_like(xd)
+        mbr.hubbard_apply(h, xd, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    y = ys[1].cpu().numpy().astype(np.float64)
+    tl = OH.terms(L, bonds, 2.0)
+    eps_p = EPS64 if prec == mbr.F64 else EPS32
+    for si, (nu, nd) in enumerate(sectors):
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        st = OH.sector(L, nu, nd)
+        rows = np.unique(np.concatenate([[0, st.size - 1], np.arange(min(st.size, 2000)),
+                                         synth.uniform_indices(50 + si, 20000, st.size)]))
+        want, ab = OH.apply(st, tl, x[o0:o1], rows=rows, with_abssum=True)
+        bad = np.abs(y[o0:o1][rows] - want) > 64 * eps_p * ab + 1e-300
+        assert not bad.any(), (nu, nd, rows[np.nonzero(bad)[0][:5]])
+
+
 @pytest.mark.parametrize("L,sectors,prec", [(6, [(3, 3), (2, 4), (0, 3), (6, 6)], 0),
                                             (8, [(4, 4), (3, 5)], 1)])
 def test_trie_ranked_product_bitwise_equals_halves(L, sectors, prec):
