@@ -1323,6 +1323,19 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
 #pragma unroll
             for (int h = 0; h < kUpMax; ++h)
                 g[h] = *reinterpret_cast<const T *>(xsb + (sob[h] + (uint32_t)rd * (uint32_t)sizeof(T)));
+            // up-hops kUpMax .. kUpMax + 3 (a fifth of the chain's blocks have
+            // them) are in flight with the first batch, where the registers
+            // allow (fp64 with bond amplitudes would drop to seven waves a SIMD)
+            constexpr bool kEarlyTail = UT || sizeof(T) == 4;
+            const bool tail = nu > (uint32_t)kUpMax;
+            T g2[4];
+            if (kEarlyTail && tail) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t t = __builtin_amdgcn_readfirstlane(lt[kUpMax + q]);
+                    g2[q] = *reinterpret_cast<const T *>(xsb + (t * cdn + (uint32_t)rd) * (uint32_t)sizeof(T));
+                }
+            }
             uint32_t hl[kWords];
             rows_load_list(slists + (size_t)rd * kWords, hl);
             const uint64_t row = c.base + (uint32_t)rd;
@@ -1335,7 +1348,23 @@ __global__ void __launch_bounds__(kBlockLanes) hv_block_kernel(HvArgs a, BlockUp
             T v = fma_t(dg, xv, UT ? tu * acc : acc);
 #pragma unroll
             for (int h = 0; h < kUpMax; ++h) v = fma_t(cf[h], g[h], v);
-            v = rows_up_tail<T, true>(xsec, lt, lc, cdn, (uint32_t)rd, nu, v);
+            // the rest in groups of four, in the order rows_up_tail sums them
+            if (!kEarlyTail) {
+                v = rows_up_tail<T, true>(xsec, lt, lc, cdn, (uint32_t)rd, nu, v);
+            } else if (tail) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v = fma_t(uniform_val(lc[kUpMax + q]), g2[q], v);
+                if (nu > (uint32_t)kUpMax + 4) {
+                    T g3[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t t = __builtin_amdgcn_readfirstlane(lt[kUpMax + 4 + q]);
+                        g3[q] = *reinterpret_cast<const T *>(xsb + (t * cdn + (uint32_t)rd) * (uint32_t)sizeof(T));
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v = fma_t(uniform_val(lc[kUpMax + 4 + q]), g3[q], v);
+                }
+            }
             if constexpr (LZ) {
                 const T uu = lz_out(v, c1, c2, pv, has_p);
                 out[row] = uu;
