@@ -511,18 +511,20 @@ def test_block_kernel_every_row_and_lanczos(bonds_kind, prec):
         want, ab = _oracle_apply_all(OH.sector(L, nu, nd), tl, x[o0:o1])
         bad = np.abs(y[o0:o1] - want) > 64 * eps_p * ab + 1e-300
         assert not bad.any(), (nu, nd, np.nonzero(bad)[0][:5])
-    # Lanczos: the fused epilogue and the per-tile partial sums of <x, u>
-    for batched in (True, False):
+    # Lanczos: the fused epilogue and the per-tile partial sums of <x, u>;
+    # with reorthogonalisation the product reads x from a row of the stored
+    # basis (the epilogue's basis mode)
+    for batched, reorth in ((True, False), (False, False), (True, True)):
         rs = []
         for G in (0, -2):
             mbr.hubbard_set_config(h, cfg["k"], G, 512)
-            rs.append(_run_lanczos(h, 30, seed=7, batched=batched))
+            rs.append(_run_lanczos(h, 30, seed=7, batched=batched, reorth=reorth))
         assert np.array_equal(rs[0][1], rs[1][1])  # steps done
         for i in (0, 2, 3):
             if prec == mbr.F64:
-                assert np.array_equal(rs[0][i], rs[1][i]), (batched, i)
+                assert np.array_equal(rs[0][i], rs[1][i]), (batched, reorth, i)
             else:
-                assert np.allclose(rs[0][i], rs[1][i], rtol=1e-5, atol=1e-6), (batched, i)
+                assert np.allclose(rs[0][i], rs[1][i], rtol=1e-5, atol=1e-6), (batched, reorth, i)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
