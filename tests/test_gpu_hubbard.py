@@ -330,8 +330,9 @@ def test_every_launch_shape_gives_identical_products():
     h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7), (6, 7)], U=[4.0] * L)
     x = torch.from_numpy(2 * synth.uniform01(21, h.dim) - 1).cuda()
     ref = _shapes_equal(h, x, (7, 14, 5))
-    with pytest.raises(mbr.MbrError):
-        mbr.hubbard_set_config(h, 7, 3, 512)
+    for bad_G in (3, -3):
+        with pytest.raises(mbr.MbrError):
+            mbr.hubbard_set_config(h, 7, bad_G, 512)
     cfg = mbr.hubbard_autotune(h, reps=2)
     say("autotuned", cfg)
     assert cfg["tuned_ms"] > 0 and cfg["G"] in (-2, -1, 0, 1, 2, 4)
