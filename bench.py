@@ -341,9 +341,10 @@ def row_trie(torch, mbr, reps):
         info = r.info()
         ms = time_launches(torch, lambda: mbr.rank_batch(r, q, out=out), reps)
         exact = bool(torch.equal(out, want))
-        # algorithmic bytes per query (the survey's count for this workload):
-        # the query in and the rank out, plus two 64-B HBM granules, one for
-        # the leaf level and one for the membership read of the state list
+        # algorithmic bytes per query: the query in and the rank out, plus
+        # two 64-B HBM granules, one for the leaf level and one for the
+        # membership read of the state list (the levels above are small
+        # enough to stay in LDS or L2)
         per_q = 8.0 + 2 * GRANULE
         roof = hbm_roofline(per_q * nq, ms, f"trie_rank_kernel ({per_q:.0f} B per query: 8 B stream + "
                                             f"2 random {GRANULE}-B granules)")
@@ -370,7 +371,7 @@ def row_trie(torch, mbr, reps):
                                "exact": bool(torch.equal(out, want)), "bytes": int(r.info().bytes),
                                "overhead_f": r.info().bytes / 4 / s.size, "records": recs,
                                "record_bytes": rbytes, "lds_levels": lds_lv,
-                               "roofline": hbm_roofline(136.0 * nq, ms, "bt_rank_kernel at the survey's "
+                               "roofline": hbm_roofline(136.0 * nq, ms, "bt_rank_kernel at the packed trie's "
                                                                         "136 B per query")}
         res[f"bitmap_k{k}"]["roofline"]["traffic"] = traffic_for(f"bt_rank_kernel<unsignedint>@k{k}")
         del r
