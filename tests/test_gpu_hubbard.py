@@ -563,6 +563,36 @@ def test_block_kernel_two_rows_per_lane_l13(prec):
         assert not bad.any(), (nu, nd, rows[np.nonzero(bad)[0][:5]])
 
 
+def test_block_shape_falls_back_to_the_tile_kernel_past_4095_rows():
+    """L = 15: C_dn = 6435 exceeds the 4095 spin-down rows the rows and block
+    kernels stage, so under G = -2 that sector goes to the tile kernel while
+    the C_dn = 1365 sector takes the block kernel; bitwise equal to G = 0 and
+    sampled rows against the oracle."""
+    L = 15
+    bonds = OH.chain_bonds(L)
+    sectors = [(2, 7), (3, 4)]          # C_dn = 6435 and 1365
+    h = mbr.hubbard_create(L, bonds, sectors, U=[3.0] * L)
+    cfg = mbr.hubbard_get_config(h)
+    x = 2 * synth.uniform01(47, h.dim) - 1
+    xd = _dev(x, mbr.F64)
+    ys = []
+    for G in (0, -2):
+        mbr.hubbard_set_config(h, cfg["k"], G, 512)
+        y = torch.empty_like(xd)
+        mbr.hubbard_apply(h, xd, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    y = ys[1].cpu().numpy()
+    tl = OH.terms(L, bonds, 3.0)
+    for si, (nu, nd) in enumerate(sectors):
+        o0, o1 = h.offsets[si], h.offsets[si + 1]
+        st = OH.sector(L, nu, nd)
+        rows = np.unique(np.concatenate([[0, st.size - 1], synth.uniform_indices(60 + si, 8000, st.size)]))
+        want, ab = OH.apply(st, tl, x[o0:o1], rows=rows, with_abssum=True)
+        bad = np.abs(y[o0:o1][rows] - want) > 64 * EPS64 * ab + 1e-300
+        assert not bad.any(), (nu, nd, rows[np.nonzero(bad)[0][:5]])
+
+
 @pytest.mark.parametrize("L,sectors,prec", [(6, [(3, 3), (2, 4), (0, 3), (6, 6)], 0),
                                             (8, [(4, 4), (3, 5)], 1)])
 def test_trie_ranked_product_bitwise_equals_halves(L, sectors, prec):
