@@ -128,6 +128,31 @@ def test_chain_l14_all_rows():
     assert torch.equal(y0, y1)
 
 
+def test_chain_l14_fp32_block_and_rows_kernels_bitwise():
+    """The fp32 L = 14 chain (the mixed-precision Lanczos of the chain row):
+    block kernel (four rows per lane) and rows kernel bitwise equal on all
+    11,778,624 rows, and sampled rows against the oracle with x rounded to
+    fp32 on both sides."""
+    L = 14
+    h = mbr.hubbard_create(L, OH.chain_bonds(L), [(7, 7)], U=[4.0] * L, precision=mbr.F32)
+    cfg = mbr.hubbard_get_config(h)
+    x = (2 * synth.uniform01(12, h.dim) - 1).astype(np.float32).astype(np.float64)
+    xd = _dev(x, mbr.F32)
+    ys = []
+    for G in (0, -2):
+        mbr.hubbard_set_config(h, cfg["k"], G, 512)
+        y = torch.empty_like(xd)
+        mbr.hubbard_apply(h, xd, y)
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    st = OH.sector(L, 7, 7)
+    rows = np.unique(np.concatenate([[0, st.size - 1], synth.uniform_indices(13, 20000, st.size)]))
+    want, ab = OH.apply(st, OH.terms(L, OH.chain_bonds(L), 4.0), x, rows=rows, with_abssum=True)
+    got = ys[1].cpu().numpy().astype(np.float64)[rows]
+    bad = np.abs(got - want) > 64 * EPS32 * ab + 1e-300
+    assert not bad.any(), rows[np.nonzero(bad)[0][:5]]
+
+
 @pytest.mark.timeout(600)
 def test_anderson_all_169_sectors_all_rows_fp32():
     L = 12
